@@ -1,0 +1,420 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test ties one part of the oracle to a library routine, a closed form, an
+invariant, or an independent brute-force quadrature (tests/bruteforce.py), so
+that a dropped term, a wrong sign, a swapped side or a transposed operand in
+the oracle fails at least one of them.  No GPU needed.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import bruteforce as BF
+import inputs as IN
+
+GAMMA = 1.4
+K_DOF = (5.0 - 3.0 * GAMMA) / (GAMMA - 1.0)
+
+
+# --------------------------------------------------------------------------
+# Quadrature, Legendre basis, mode order, mass matrix (Section 3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_gauss_legendre_matches_numpy(orc, n):
+    x, w = orc.gauss(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    np.testing.assert_allclose(x, xr, atol=1e-15)
+    np.testing.assert_allclose(w, wr, atol=1e-15)
+
+
+def test_legendre_matches_numpy(orc):
+    from numpy.polynomial import legendre as npl
+
+    for x in np.linspace(-1, 1, 11):
+        P, dP = orc.legendre(5, x)
+        for l in range(6):
+            c = np.zeros(l + 1)
+            c[l] = 1.0
+            assert abs(P[l] - npl.legval(x, c)) < 1e-14
+            assert abs(dP[l] - npl.legval(x, npl.legder(c))) < 1e-13
+
+
+def test_mode_order_and_counts(orc):
+    # dim P_k = (k+1)(k+2)(k+3)/6 (P1: 4, P2: 10, P3: 20)
+    for k in (1, 2, 3):
+        assert orc.nmodes(k) == (k + 1) * (k + 2) * (k + 3) // 6
+    m2 = orc.modes(2).tolist()
+    assert m2 == [[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [2, 0, 0], [1, 1, 0], [1, 0, 1], [0, 2, 0],
+                  [0, 1, 1], [0, 0, 2]]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_mass_matrix_is_orthogonality(orc, k):
+    md = orc.modes(k)
+    for a in range(len(md)):
+        for b in range(len(md)):
+            M = orc.mass_entry(k, a, b)
+            expect = 1.0 / np.prod(2 * md[a] + 1) if a == b else 0.0
+            assert abs(M - expect) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Maxwellian moments (Section 2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("U,lam", [(0.3, 0.7), (-1.2, 2.0), (0.0, 0.25), (1.4, 0.007)])
+def test_moments_vs_scipy_quad(orc, U, lam):
+    dens = lambda u: np.sqrt(lam / np.pi) * np.exp(-lam * (u - U) ** 2)
+    for side, (a, b) in ((0, (-np.inf, np.inf)), (1, (0.0, np.inf)), (-1, (-np.inf, 0.0))):
+        mu, mx = orc.moments(U, lam, K_DOF, side)
+        for n in range(9):
+            ref, _ = integrate.quad(lambda u: u ** n * dens(u), a, b, epsabs=1e-15, epsrel=1e-13, limit=200)
+            scale = max(1.0, abs(ref))
+            assert abs(mu[n] - ref) <= 2e-12 * scale, (side, n, mu[n], ref)
+    # half spaces add to the full space
+    f, _ = orc.moments(U, lam, K_DOF, 0)
+    p, _ = orc.moments(U, lam, K_DOF, 1)
+    m, _ = orc.moments(U, lam, K_DOF, -1)
+    np.testing.assert_allclose(p + m, f, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("K", [1.0, 2.0, 3.0])
+def test_internal_dof_moments_vs_brute_force(orc, K):
+    # xi = (xi_1..xi_K) i.i.d. N(0, 1/(2 lambda)): <xi^2>, <xi^4> by Gauss-Hermite
+    lam = 0.8
+    from numpy.polynomial.hermite_e import hermegauss
+
+    x, w = hermegauss(12)
+    w = w / w.sum()
+    s = 1.0 / np.sqrt(2 * lam)
+    grids = np.meshgrid(*([s * x] * int(K)), indexing="ij")
+    wt = np.ones_like(grids[0])
+    for g in np.meshgrid(*([w] * int(K)), indexing="ij"):
+        wt = wt * g
+    xi2 = sum(g * g for g in grids)
+    _, mx = orc.moments(0.0, lam, K, 0)
+    assert abs(mx[0] - 1.0) < 1e-15
+    assert abs(mx[1] - np.sum(wt * xi2)) < 1e-13
+    assert abs(mx[2] - np.sum(wt * xi2 ** 2)) < 1e-13
+
+
+def test_slope_solve_vs_dense_quadrature(orc):
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        U = rng.uniform(-1.5, 1.5, 3)
+        lam = rng.uniform(0.1, 2.0)
+        b = rng.normal(size=5)
+        a, M = orc.slope(U, lam, K_DOF, b)
+        G = BF.MaxwellQuad(U[0], U[1], U[2], lam, K_DOF)
+        Mq = G.m5()
+        np.testing.assert_allclose(M, Mq, rtol=1e-12, atol=1e-12)
+        aq = np.linalg.solve(Mq, b)
+        np.testing.assert_allclose(a, aq, rtol=1e-9, atol=1e-10 * np.abs(aq).max())
+        np.testing.assert_allclose(Mq @ a, b, rtol=1e-10, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Time integrals of Eq. (flux) and the linear-in-time fit
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("tau,delta", [(1e-3, 1e-2), (2e-2, 1e-2), (1e-1, 1e-2), (5e-6, 6.7e-4)])
+def test_time_integrals_vs_quad(orc, tau, delta):
+    factors = [
+        lambda t: 1 - np.exp(-t / tau),
+        lambda t: (t + tau) * np.exp(-t / tau) - tau,
+        lambda t: t - tau + tau * np.exp(-t / tau),
+        lambda t: np.exp(-t / tau),
+        lambda t: (t + tau) * np.exp(-t / tau),
+        lambda t: tau * np.exp(-t / tau),
+    ]
+    c = orc.time_integrals(tau, delta)
+    for i, f in enumerate(factors):
+        ref, _ = integrate.quad(f, 0, delta, epsabs=1e-17, epsrel=1e-13, points=[min(tau, delta / 2)], limit=200)
+        assert abs(c[i] - ref) <= 1e-11 * max(abs(ref), delta * tau, 1e-300), (i, c[i], ref)
+
+
+def test_time_integrals_inviscid_limit(orc):
+    d = 0.01
+    np.testing.assert_allclose(orc.time_integrals(0.0, d), [d, 0, d * d / 2, 0, 0, 0], atol=0, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# Volume flux, Eq. (flux-2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("low_mach", [False, True])
+def test_volume_flux_vs_bruteforce(orc, low_mach):
+    rng = np.random.default_rng(3 + low_mach)
+    for mu, pr in ((0.0, 1.0), (0.02, 1.0), (1 / 1600, 0.72), (0.3, 0.72)):
+        c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=pr)
+        for _ in range(3):
+            q = IN.point_state(rng, low_mach)
+            dq = IN.point_gradient(rng)
+            F, Ft = orc.volume_flux(c, q, dq)
+            Fb, Ftb = BF.volume_flux(GAMMA, mu, pr, q, dq)
+            assert np.abs(F - Fb).max() <= 1e-13 * np.abs(Fb).max()
+            assert np.abs(Ft - Ftb).max() <= 1e-12 * np.abs(Ftb).max()
+
+
+@pytest.mark.parametrize("mu,pr", [(0.0, 1.0), (0.05, 1.0), (0.05, 0.72), (1 / 1600, 0.72)])
+def test_volume_flux_recovers_navier_stokes(orc, mu, pr):
+    rng = np.random.default_rng(5)
+    c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=pr)
+    for lm in (False, True):
+        for _ in range(4):
+            q = IN.point_state(rng, lm)
+            dq = IN.point_gradient(rng)
+            F, _ = orc.volume_flux(c, q, dq)
+            Fn = BF.ns_flux(GAMMA, mu, pr, q, dq)
+            assert np.abs(F - Fn).max() <= 1e-12 * np.abs(Fn).max()
+
+
+def test_volume_flux_time_derivative_is_euler_jacobian(orc):
+    rng = np.random.default_rng(6)
+    c = orc.make_cfg((1, 1, 1), 2, mu=0.01, prandtl=0.72)
+    for lm in (False, True):
+        for _ in range(4):
+            q = IN.point_state(rng, lm)
+            dq = IN.point_gradient(rng)
+            _, Ft = orc.volume_flux(c, q, dq)
+            qt = -sum(BF.euler_jvp(q, e, dq[e], GAMMA) for e in range(3))
+            for d in range(3):
+                ref = BF.euler_jvp(q, d, qt, GAMMA)
+                assert np.abs(Ft[d] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1.0)
+
+
+# --------------------------------------------------------------------------
+# Face flux, Eq. (flux) + slopes + time fit
+# --------------------------------------------------------------------------
+FACE_CASES = [(0.0, 1.0, 1e-2), (1e-6, 1.0, 1e-2), (1e-4, 0.72, 1e-2), (1e-2, 0.72, 1e-2), (0.1, 0.72, 1e-3)]
+
+
+@pytest.mark.parametrize("mu,pr,dt", FACE_CASES)
+def test_face_flux_vs_bruteforce(orc, mu, pr, dt):
+    rng = np.random.default_rng(int(1e6 * mu) + 17)
+    c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=pr)
+    for d in range(3):
+        qL, qR = IN.point_state(rng), IN.point_state(rng)
+        dqL, dqR = IN.point_gradient(rng), IN.point_gradient(rng)
+        F, Ft = orc.face_flux(c, dt, d, qL, dqL, qR, dqR)
+        Fb, Ftb = BF.face_flux(GAMMA, mu, pr, dt, d, qL, dqL, qR, dqR)
+        assert np.abs(F - Fb).max() <= 1e-12 * np.abs(Fb).max(), (d, F, Fb)
+        assert np.abs(Ft - Ftb).max() <= 1e-10 * np.abs(Ftb).max(), (d, Ft, Ftb)
+
+
+def test_face_flux_low_mach_vs_bruteforce(orc):
+    rng = np.random.default_rng(23)
+    mu, pr, dt = 1 / 1600, 0.72, 6.67782e-4
+    c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=pr)
+    for d in range(3):
+        qL = IN.point_state(rng, True)
+        qR = qL + rng.normal(0, 0.01, 5)  # nearly continuous, as in a smooth flow
+        dqL, dqR = IN.point_gradient(rng), IN.point_gradient(rng)
+        F, Ft = orc.face_flux(c, dt, d, qL, dqL, qR, dqR)
+        Fb, Ftb = BF.face_flux(GAMMA, mu, pr, dt, d, qL, dqL, qR, dqR)
+        assert np.abs(F - Fb).max() <= 1e-12 * np.abs(Fb).max()
+        assert np.abs(Ft - Ftb).max() <= 1e-8 * np.abs(Ftb).max()
+
+
+@pytest.mark.parametrize("mu", [0.0, 1e-4, 0.05, 2.0])
+def test_face_flux_equal_states_is_euler_flux(orc, mu):
+    rng = np.random.default_rng(7)
+    c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=0.72)
+    z = np.zeros((3, 5))
+    for lm in (False, True):
+        q = IN.point_state(rng, lm)
+        for d in range(3):
+            F, Ft = orc.face_flux(c, 1e-2, d, q, z, q, z)
+            ref = BF.euler_flux(q, d, GAMMA)
+            assert np.abs(F - ref).max() <= 1e-13 * np.abs(ref).max()
+            assert np.abs(Ft).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mu,pr", [(0.0, 1.0), (1e-3, 0.72), (0.05, 0.72)])
+def test_face_flux_continuous_data_equals_volume_flux(orc, mu, pr):
+    # With q_L = q_R and equal gradients all e^{-t/tau} terms cancel and the
+    # face distribution reduces to the volume form g0 (1 - tau (a.u + A) + A t).
+    rng = np.random.default_rng(8)
+    c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=pr)
+    for lm in (False, True):
+        q = IN.point_state(rng, lm)
+        dq = IN.point_gradient(rng)
+        Fv, Ftv = orc.volume_flux(c, q, dq)
+        for d in range(3):
+            F, Ft = orc.face_flux(c, 1e-2, d, q, dq, q, dq)
+            assert np.abs(F - Fv[d]).max() <= 1e-12 * np.abs(Fv[d]).max()
+            assert np.abs(Ft - Ftv[d]).max() <= 2e-9 * np.abs(Ftv[d]).max()
+
+
+# --------------------------------------------------------------------------
+# Grid-level invariants (Section 3 operator, Eq. (two-stage))
+# --------------------------------------------------------------------------
+def _uniform(orc, cfg, Q):
+    q = np.zeros(orc.field_shape(cfg))
+    q[:, 0] = np.asarray(Q)[:, None, None, None]
+    return q
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_free_stream_preservation(orc, k):
+    c = orc.make_cfg((4, 3, 5), k, lo=(0, 0, 0), hi=(1, 2, 3), mu=0.01, prandtl=0.72)
+    Q = [1.2, 0.3, -0.4, 0.5, 3.0]
+    q = _uniform(orc, c, Q)
+    L, Lt = orc.residual(c, q, 1e-2)
+    assert np.abs(L).max() < 1e-13 and np.abs(Lt).max() < 1e-13
+    q2 = orc.step(c, q, 1e-2, 3)
+    assert np.abs(q2 - q).max() < 1e-14
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_conservation(orc, k):
+    rng = np.random.default_rng(9)
+    c = orc.make_cfg((5, 4, 6), k, lo=(0, 0, 0), hi=(1, 1.5, 2), mu=0.01, prandtl=0.72)
+    q = IN.random_field(rng, (5, 4, 6), orc.nmodes(k), amp=0.05)
+    tot0 = q[:, 0].sum(axis=(1, 2, 3))
+    q2 = orc.step(c, q, 2e-3, 3)
+    tot1 = q2[:, 0].sum(axis=(1, 2, 3))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(tot0).max())
+
+
+def test_s2o4_amplification(orc):
+    for z in (-0.3, 0.7, -2.0, 1.1):
+        dt = 0.5
+        zd = z * dt
+        assert abs(orc.s2o4_linear(z, dt, 1) - (1 + zd + zd ** 2 / 2 + zd ** 3 / 6 + zd ** 4 / 24)) < 1e-15
+
+
+def _order_run(orc, k, N, axis, t_end=0.5, cfl=0.2):
+    shape = [1, 1, 1]
+    shape[axis] = N
+    c = orc.make_cfg(shape, k, lo=(0, 0, 0), hi=(2, 2, 2))
+    prob = "advection_" + "xyz"[axis]
+    q = orc.project(c, prob)
+    amax = 1.0 + np.sqrt(GAMMA / 0.8)
+    n = int(np.ceil(t_end / (cfl * (2.0 / N) / amax)))
+    q = orc.step(c, q, t_end / n, n)
+    return orc.advection_error(c, q, t_end, prob)
+
+
+@pytest.mark.parametrize("k,axis", [(1, 0), (2, 0), (2, 1), (2, 2)])
+def test_convergence_order_1d_advection(orc, k, axis):
+    # exact solution rho = 1 + 0.2 sin(pi (x - t)), Section 5.1 in one axis
+    e = [_order_run(orc, k, N, axis) for N in (8, 16, 32)]
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all(np.abs(orders - (k + 1)) < 0.3), orders
+
+
+def test_convergence_order_3d_advection(orc):
+    # Section 5.1 3-D problem, rho = 1 + 0.2 sin(pi (x + y + z - 3 t)), P2
+    errs = []
+    for N in (4, 8):
+        c = orc.make_cfg((N, N, N), 2, lo=(0, 0, 0), hi=(2, 2, 2))
+        q = orc.project(c, "advection")
+        amax = 1.0 + np.sqrt(GAMMA / 0.8)
+        n = int(np.ceil(0.25 / (0.2 * (2.0 / N) / amax)))
+        q = orc.step(c, q, 0.25 / n, n)
+        errs.append(orc.advection_error(c, q, 0.25))
+    assert abs(np.log2(errs[0] / errs[1]) - 3.0) < 0.3
+
+
+def test_tgv_initial_kinetic_energy(orc):
+    c = orc.make_cfg((16, 16, 16), 2, lo=(-np.pi,) * 3, hi=(np.pi,) * 3)
+    q = orc.project(c, "tgv")
+    Ek = orc.kinetic_energy(c, q) / (2 * np.pi) ** 3
+    assert abs(Ek - 0.125) < 1e-4
+
+
+def test_projection_cell_average(orc):
+    c = orc.make_cfg((3, 3, 3), 2, lo=(-np.pi,) * 3, hi=(np.pi,) * 3)
+    q = orc.project(c, "tgv")
+    dx = 2 * np.pi / 3
+    i, j, k = 1, 2, 0
+    x0, y0, z0 = -np.pi + i * dx, -np.pi + j * dx, -np.pi + k * dx
+    f = lambda z, y, x: np.sin(x) * np.cos(y) * np.cos(z)
+    ref, _ = integrate.tplquad(f, x0, x0 + dx, y0, y0 + dx, z0, z0 + dx, epsabs=1e-13)
+    assert abs(q[1, 0, k, j, i] - ref / dx ** 3) < 1e-9
+
+
+def _swap_xy(orc, q, k):
+    md = orc.modes(k).tolist()
+    perm = [md.index([m[1], m[0], m[2]]) for m in md]
+    out = q[:, perm].transpose(0, 1, 2, 4, 3).copy()
+    out[[1, 2]] = out[[2, 1]]
+    return out
+
+
+def test_axis_permutation_symmetry(orc):
+    rng = np.random.default_rng(12)
+    k = 2
+    c = orc.make_cfg((4, 4, 3), k, lo=(0, 0, 0), hi=(1, 1, 0.8), mu=0.01, prandtl=0.72)
+    q = IN.random_field(rng, (4, 4, 3), orc.nmodes(k), amp=0.05)
+    L, Lt = orc.residual(c, q, 1e-2)
+    Ls, Lts = orc.residual(c, _swap_xy(orc, q, k), 1e-2)
+    assert np.abs(Ls - _swap_xy(orc, L, k)).max() <= 1e-12 * np.abs(L).max()
+    assert np.abs(Lts - _swap_xy(orc, Lt, k)).max() <= 1e-12 * np.abs(Lt).max()
+
+
+def test_residual_cells_and_slab_match_full_grid(orc):
+    rng = np.random.default_rng(13)
+    c = orc.make_cfg((5, 4, 6), 2, lo=(0, 0, 0), hi=(1, 1, 1), mu=0.01, prandtl=0.72)
+    q = IN.random_field(rng, (5, 4, 6), 10)
+    L, Lt = orc.residual(c, q, 1e-2)
+    cells = [0, 7, 19, 119, 60]
+    Lc, Ltc = orc.residual_cells(c, q, 1e-2, cells)
+    Lf = L.reshape(5, 10, -1)
+    Ltf = Lt.reshape(5, 10, -1)
+    for t, cc in enumerate(cells):
+        assert np.array_equal(Lc[t], Lf[:, :, cc])
+        assert np.array_equal(Ltc[t], Ltf[:, :, cc])
+    Ls, Lts = orc.residual_slab(c, q, 1e-2, 2, 4)
+    n = 5 * 4
+    assert np.array_equal(Ls, Lf[:, :, 2 * n:4 * n].transpose(2, 0, 1))
+    assert np.array_equal(Lts, Ltf[:, :, 2 * n:4 * n].transpose(2, 0, 1))
+
+
+# --------------------------------------------------------------------------
+# Forward-mode dual numbers (the oracle gradient) against central differences
+# --------------------------------------------------------------------------
+def test_dual_point_fluxes_vs_central_differences(orc):
+    rng = np.random.default_rng(14)
+    mu = 0.01
+    c = orc.make_cfg((1, 1, 1), 2, mu=mu, prandtl=0.72)
+    q, dq = IN.point_state(rng), IN.point_gradient(rng)
+    tq, tdq, tmu = rng.normal(size=5), rng.normal(size=(3, 5)), 0.3
+    F, dF, Ft, dFt = orc.volume_flux_jvp(c, q, dq, tq, tdq, tmu)
+    h = 1e-6
+    cp = orc.make_cfg((1, 1, 1), 2, mu=mu + h * tmu, prandtl=0.72)
+    cm = orc.make_cfg((1, 1, 1), 2, mu=mu - h * tmu, prandtl=0.72)
+    Fp, Ftp = orc.volume_flux(cp, q + h * tq, dq + h * tdq)
+    Fm, Ftm = orc.volume_flux(cm, q - h * tq, dq - h * tdq)
+    np.testing.assert_allclose(dF, (Fp - Fm) / (2 * h), rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(dFt, (Ftp - Ftm) / (2 * h), rtol=1e-6, atol=1e-7)
+    x = np.concatenate([IN.point_state(rng), IN.point_gradient(rng).ravel(), IN.point_state(rng),
+                        IN.point_gradient(rng).ravel()])
+    tx = rng.normal(size=40)
+    dt = 1e-2
+    for d in range(3):
+        F, dF, Ft, dFt = orc.face_flux_jvp(c, dt, d, x, tx, tmu)
+        xp, xm = x + h * tx, x - h * tx
+        Fp, Ftp = orc.face_flux(cp, dt, d, xp[:5], xp[5:20], xp[20:25], xp[25:])
+        Fm, Ftm = orc.face_flux(cm, dt, d, xm[:5], xm[5:20], xm[20:25], xm[25:])
+        np.testing.assert_allclose(dF, (Fp - Fm) / (2 * h), rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(dFt, (Ftp - Ftm) / (2 * h), rtol=1e-5, atol=1e-5)
+
+
+def test_dual_step_and_energy_vs_central_differences(orc):
+    rng = np.random.default_rng(15)
+    mu = 0.01
+    shape = (4, 3, 3)
+    mk = lambda m: orc.make_cfg(shape, 1, lo=(0, 0, 0), hi=(1, 1, 1), mu=m, prandtl=0.72)
+    c = mk(mu)
+    q = IN.random_field(rng, shape, orc.nmodes(1), amp=0.05)
+    v = IN.random_direction(rng, q) * 1e-2
+    dt, n = 2e-3, 2
+    # direction in the coefficients (h = 1e-3) and in mu (h = 1e-6): the
+    # step sizes keep truncation and round-off of the differences below 1e-8
+    for tmu, vv, h in ((0.0, v, 1e-3), (0.5, 0 * v, 1e-6)):
+        qN, dqN = orc.step_jvp(c, q, vv, tmu, dt, n)
+        assert np.array_equal(qN, orc.step(c, q, dt, n))
+        J, dJ = orc.ke_jvp(c, qN, dqN)
+        assert abs(J - orc.kinetic_energy(c, qN)) <= 1e-15 * abs(J)
+        Jp = orc.kinetic_energy(c, orc.step(mk(mu + h * tmu), q + h * vv, dt, n))
+        Jm = orc.kinetic_energy(c, orc.step(mk(mu - h * tmu), q - h * vv, dt, n))
+        assert abs(dJ - (Jp - Jm) / (2 * h)) <= 1e-8 * abs(dJ)

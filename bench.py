@@ -1,0 +1,156 @@
+"""Benchmark: P2 Taylor-Green vortex, 128^3 cells, one S2O4 step of the DG
+gas-kinetic scheme per timed step, on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-adjoint]
+
+Prints one JSON line.  `value` is the FP32-bulk path's throughput in
+DOF-updates/s (5 variables x 10 modes x 128^3 cells per step / seconds per
+step); the FP64 path, the FP32-vs-FP64 relative L2 difference, the
+adjoint/forward time ratio, a roofline entry for the dominant kernel (from
+HIP events recorded by the library on its stream) and the FP64 CPU oracle
+timed on a bounded sample (cpu_baseline) are reported beside it.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Algorithmic work per unit, from paper_2202_13821_amd/csrc/flopcount (see
+# the package's flops.json): floating-point operations per face point and per
+# volume point of each stage, for the kernels' own formulas.
+FLOPS_JSON = os.path.join(ROOT, "paper_2202_13821_amd", "flops.json")
+
+MI355X_PEAK = {"fp32_vector": 157.3, "fp64_vector": 78.6, "hbm_GBs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128, help="cells per axis")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def load_flops():
+    if os.path.exists(FLOPS_JSON):
+        with open(FLOPS_JSON) as f:
+            return json.load(f)
+    return None
+
+
+def time_path(precision, n, steps, warmup, timing=True):
+    import torch
+
+    from paper_2202_13821_amd import Solver, problems
+
+    q0, lo, hi = problems.tgv((n, n, n), 2)
+    dt = problems.tgv_dt(n)
+    s = Solver((n, n, n), lo, hi, 2, mu=1.0 / 1600.0, prandtl=0.72, precision=precision, device="cuda:0")
+    q = torch.as_tensor(q0, device="cuda:0")
+    s.step(q, dt, warmup)
+    s.check()
+    if timing:
+        s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(q, dt, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = s.get_timing() if timing else None
+    s.set_timing(False)
+    s.check()
+    return (t1 - t0) / steps, kern, q, s
+
+
+def cpu_baseline(n, seconds):
+    """FP64 oracle operator on whole z-slabs of the same 128^3 Taylor-Green
+    state (each face of the slab computed once), two evaluations per step."""
+    import oracle as O
+    from paper_2202_13821_amd import problems
+
+    q0, lo, hi = problems.tgv((n, n, n), 2)
+    c = O.make_cfg((n, n, n), 2, lo=lo, hi=hi, mu=1 / 1600, prandtl=0.72)
+    dt = problems.tgv_dt(n)
+    k1 = 1
+    t0 = time.perf_counter()
+    O.residual_slab(c, q0, dt, 0, k1)
+    el = time.perf_counter() - t0
+    # grow the slab until the sample is long enough
+    if el < seconds:
+        k1 = max(1, min(n, int(k1 * seconds / max(el, 1e-3))))
+        t0 = time.perf_counter()
+        O.residual_slab(c, q0, dt, 0, k1)
+        el = time.perf_counter() - t0
+    cells = n * n * k1
+    per_step = 2.0 * el / cells  # seconds per cell per step
+    return {"value": 50.0 / per_step, "unit": "DOF-updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"oracle L and L_t on z-slab of {k1} x {n}^2 cells of the {n}^3 P2 TGV state "
+                      f"({el:.1f} s), x2 evaluations per step"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is a design "
+              "in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    n = a.n
+    dof = 5 * 10 * n ** 3
+    out = {"metric": "P2 TGV 128^3 DOF-updates/s, FP32-bulk vs FP64 at stated L2 error; adj/fwd",
+           "unit": "DOF-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (analytic Taylor-Green initial data, L2-projected)",
+           "config": {"workload": f"DG-HGKS P2 Taylor-Green vortex {n}^3 cells, 3x3x3 volume / 3x3 face "
+                                  "Gauss points, Re 1600, Ma 0.1, Pr 0.72, CFL 0.15, FP32-bulk flux and "
+                                  "projection with FP64 stage accumulation",
+                      "cells": n ** 3, "modes": 10, "dof_per_step": dof}}
+    sec32, k32, q32, s32 = time_path("fp32_bulk", n, a.steps, a.warmup)
+    out["value"] = dof / sec32
+    out["ms_per_step"] = 1e3 * sec32
+    out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else None) for k, v in k32.items()}
+    flops = load_flops()
+    face_ms = k32["face"][0] / max(k32["face"][1], 1)
+    vol_ms = k32["volume"][0] / max(k32["volume"][1], 1)
+    out["kernels_ms_per_step"] = {"face": 2 * face_ms, "volume": 2 * vol_ms}
+    if flops:
+        # face launches alternate stage 1 (F and Ft) / stage 2 (Ft only): average work per launch
+        npts_face = 3 * n ** 3 * 9
+        w = 0.5 * (flops["fp32"]["face_stage1"] + flops["fp32"]["face_stage2"]) * npts_face
+        achieved = w / (face_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "face_kernel<float,2,3>", "achieved": achieved,
+                           "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
+                           "frac": achieved / MI355X_PEAK["fp32_vector"], "traffic": None,
+                           "flops_per_point": 0.5 * (flops["fp32"]["face_stage1"] + flops["fp32"]["face_stage2"])}
+    if not a.no_fp64:
+        del s32
+        sec64, k64, q64, s64 = time_path("fp64", n, a.steps, a.warmup)
+        out["fp64"] = {"value": dof / sec64, "ms_per_step": 1e3 * sec64,
+                       "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in k64.items()}}
+        out["speedup_fp32_bulk_vs_fp64"] = sec64 / sec32
+        d = (q32 - q64).reshape(5, -1)
+        r = q64.reshape(5, -1)
+        groups = ((0,), (1, 2, 3), (4,))
+        out["rel_l2_fp32_bulk_vs_fp64"] = max(
+            float(torch.linalg.norm(d[list(g)]) / torch.linalg.norm(r[list(g)])) for g in groups)
+        del s64
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

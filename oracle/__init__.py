@@ -71,6 +71,7 @@ def lib():
             "orc_residual_cells": (None, [cp, dp, d, P(i64), i64, dp, dp]),
             "orc_residual_slab": (None, [cp, dp, d, i, i, dp, dp]),
             "orc_step": (None, [cp, dp, d, i]),
+            "orc_step_cells": (None, [cp, dp, d, P(i64), i64, dp]),
             "orc_project": (None, [cp, i, dp]),
             "orc_kinetic_energy": (d, [cp, dp]),
             "orc_advection_error": (d, [cp, dp, d, i, i]),
@@ -205,6 +206,16 @@ def residual_slab(cfg, q, dt, k0, k1):
     Lt = np.zeros_like(L)
     lib().orc_residual_slab(ctypes.byref(cfg), _p(q), float(dt), int(k0), int(k1), _p(L), _p(Lt))
     return L, Lt
+
+
+def step_cells(cfg, q, dt, cells):
+    """Q^{n+1} of one step at the listed flat cell indices; shape (ncells, 5, nmodes)."""
+    q = _f64(q, field_shape(cfg))
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    out = np.zeros((len(cells), 5, nmodes(cfg.k)))
+    lib().orc_step_cells(ctypes.byref(cfg), _p(q), float(dt), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         len(cells), _p(out))
+    return out
 
 
 def step(cfg, q, dt, nsteps=1):

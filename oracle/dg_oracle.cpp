@@ -882,19 +882,67 @@ static void residual_slab(const Disc& D, double mu, double dt, const double* q, 
 // Q^{n+1} = Q^n + dt L(Q^n) + dt^2/6 (L_t(Q^n) + 2 L_t(Q*)).  `op(Q, L, Lt)`
 // evaluates the operator; the stage at t* = t_n + dt/2 uses the same time
 // windows [0, dt] and [0, dt/2] measured from t*.
+template <class R>
+static inline R stage_star(R qn, R L, R Lt, double dt) {
+  return qn + R(0.5 * dt) * L + R(dt * dt / 8.0) * Lt;
+}
+template <class R>
+static inline R stage_final(R qn, R L, R Lt, R Lt_star, double dt) {
+  return qn + R(dt) * L + R(dt * dt / 6.0) * (Lt + R(2.0) * Lt_star);
+}
+
 template <class R, class Op>
 static void s2o4_update(size_t n, double dt, R* q, Op op) {
   std::vector<R> L(n), Lt(n), Qs(n), L2(n), Lt2(n);
   op(q, L.data(), Lt.data());
-  for (size_t i = 0; i < n; ++i) Qs[i] = q[i] + R(0.5 * dt) * L[i] + R(dt * dt / 8.0) * Lt[i];
+  for (size_t i = 0; i < n; ++i) Qs[i] = stage_star(q[i], L[i], Lt[i], dt);
   op(Qs.data(), L2.data(), Lt2.data());
-  for (size_t i = 0; i < n; ++i) q[i] = q[i] + R(dt) * L[i] + R(dt * dt / 6.0) * (Lt[i] + R(2.0) * Lt2[i]);
+  for (size_t i = 0; i < n; ++i) q[i] = stage_final(q[i], L[i], Lt[i], Lt2[i], dt);
 }
 
 template <class R>
 static void s2o4_step(const Disc& D, R mu, double dt, R* q) {
   const size_t n = (size_t)5 * D.nm * D.ncell;
   s2o4_update(n, dt, q, [&](const R* x, R* L, R* Lt) { residual(D, mu, dt, x, L, Lt); });
+}
+
+// One S2O4 step evaluated only where it is needed to return Q^{n+1} at the
+// listed cells: stage 1 on the cells and their six face neighbours, stage 2
+// on the listed cells.  Output layout [cell_in_list][var][mode].
+static void step_cells(const Disc& D, double mu, double dt, const double* q, const int64_t* cells, int64_t ncells,
+                       double* out) {
+  const int nm = D.nm;
+  std::vector<int64_t> s1;
+  for (int64_t t = 0; t < ncells; ++t) {
+    s1.push_back(cells[t]);
+    for (int d = 0; d < 3; ++d) {
+      s1.push_back(D.neighbor(cells[t], d, -1));
+      s1.push_back(D.neighbor(cells[t], d, +1));
+    }
+  }
+  std::sort(s1.begin(), s1.end());
+  s1.erase(std::unique(s1.begin(), s1.end()), s1.end());
+  const int64_t n1 = (int64_t)s1.size();
+  std::vector<double> L(n1 * 5 * nm), Lt(n1 * 5 * nm);
+  residual_cells(D, mu, dt, q, s1.data(), n1, L.data(), Lt.data());
+  std::vector<double> qs(q, q + (size_t)5 * nm * D.ncell);
+  for (int64_t t = 0; t < n1; ++t)
+    for (int v = 0; v < 5; ++v)
+      for (int n = 0; n < nm; ++n) {
+        size_t gi = D.idx(v, n, s1[t]);
+        qs[gi] = stage_star(q[gi], L[(t * 5 + v) * nm + n], Lt[(t * 5 + v) * nm + n], dt);
+      }
+  std::vector<double> L2(ncells * 5 * nm), Lt2(ncells * 5 * nm);
+  residual_cells(D, mu, dt, qs.data(), cells, ncells, L2.data(), Lt2.data());
+  for (int64_t t = 0; t < ncells; ++t) {
+    int64_t r = std::lower_bound(s1.begin(), s1.end(), cells[t]) - s1.begin();
+    for (int v = 0; v < 5; ++v)
+      for (int n = 0; n < nm; ++n) {
+        size_t gi = D.idx(v, n, cells[t]);
+        out[(t * 5 + v) * nm + n] = stage_final(q[gi], L[(r * 5 + v) * nm + n], Lt[(r * 5 + v) * nm + n],
+                                                Lt2[(t * 5 + v) * nm + n], dt);
+      }
+  }
 }
 
 // L^2 projection of a pointwise state onto the P_k basis (6-point rule).
@@ -1123,6 +1171,11 @@ void orc_residual_cells(const Cfg* c, const double* q, double dt, const int64_t*
 void orc_residual_slab(const Cfg* c, const double* q, double dt, int k0, int k1, double* L, double* Lt) {
   Disc D(*c);
   residual_slab(D, c->mu, dt, q, k0, k1, L, Lt);
+}
+
+void orc_step_cells(const Cfg* c, const double* q, double dt, const int64_t* cells, int64_t n, double* out) {
+  Disc D(*c);
+  step_cells(D, c->mu, dt, q, cells, n, out);
 }
 
 void orc_step(const Cfg* c, double* q, double dt, int nsteps) {

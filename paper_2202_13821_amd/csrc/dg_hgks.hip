@@ -1,0 +1,514 @@
+// dg_hgks.hip -- host side of the C-ABI in include/dg_hgks.h: parameter
+// validation, workspace carving, the launch sequence of the S2O4 step and of
+// its adjoint, per-kernel event timing and error reporting.
+//
+// Launch sequence of one step (Eq. (two-stage)), all on the caller's stream:
+//   stage 1: face_kernel<F and Ft>   volume_kernel<MODE 0>  -> Q*, P
+//   stage 2: face_kernel<Ft only>    volume_kernel<MODE 1>  -> Q^{n+1}
+// In FP32-bulk mode the kernels read a float copy of the coefficients (written
+// by the stage-2 update for the next step) while Q^n, P and Q^{n+1} stay FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_hgks.h"
+#include "kernels_fwd.hpp"
+#include "kernels_adj.hpp"
+
+using namespace dgk;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t flag = 0, qs = 0, qstar = 0, P = 0, rec = 0;
+  size_t adj_states = 0, adj_stars = 0, adj_qbar = 0, adj_qsbar = 0, adj_Lbar = 0, adj_Ltbar = 0, adj_frec = 0,
+         adj_mu = 0, adj_tmp = 0;
+  size_t total = 0;
+};
+
+struct TimingRec {
+  int cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct dg_hgks_ctx {
+  dg_hgks_params p{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int max_stride = 0;
+  Layout lay;
+  long long ncell = 0;
+  int nm = 0, nt = 0;
+  double mu = 0.0;
+  bool flag_ready = false;
+  std::string err;
+  bool timing = false;
+  std::vector<TimingRec> trecs;
+  double t_ms[5] = {0, 0, 0, 0, 0};
+  long long t_n[5] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(dg_hgks_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_init_error = msg;
+  return code;
+}
+
+#define DG_HIP(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, DG_HGKS_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+bool supported(int k, int nq) { return (k == 1 && nq == 2) || (k == 2 && nq == 3) || (k == 2 && nq == 2); }
+
+int validate(const dg_hgks_params* p, std::string& why) {
+  if (!p) { why = "params is NULL"; return DG_HGKS_EINVAL; }
+  if (p->struct_size != sizeof(dg_hgks_params)) { why = "params.struct_size != sizeof(dg_hgks_params)"; return DG_HGKS_EINVAL; }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "grid sizes must be >= 1"; return DG_HGKS_EINVAL; }
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) { why = "too many cells"; return DG_HGKS_EINVAL; }
+  for (int e = 0; e < 3; ++e)
+    if (!(p->hi[e] > p->lo[e]) || !std::isfinite(p->hi[e] - p->lo[e])) { why = "need hi > lo on every axis"; return DG_HGKS_EINVAL; }
+  if (p->degree < 1 || p->degree > 2) { why = "degree must be 1 or 2"; return DG_HGKS_EINVAL; }
+  const int nq = p->nq ? p->nq : p->degree + 1;
+  if (nq < 1 || nq > 4) { why = "nq must be in [1, 4]"; return DG_HGKS_EINVAL; }
+  if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) { why = "gamma must be > 1"; return DG_HGKS_EINVAL; }
+  if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) { why = "mu must be >= 0"; return DG_HGKS_EINVAL; }
+  if (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl)) { why = "prandtl must be > 0"; return DG_HGKS_EINVAL; }
+  if (p->precision != DG_HGKS_FP64 && p->precision != DG_HGKS_FP32_BULK) { why = "unknown precision"; return DG_HGKS_EINVAL; }
+  if (!supported(p->degree, nq)) { why = "(degree, nq) combination not compiled"; return DG_HGKS_EUNSUPPORTED; }
+  return DG_HGKS_OK;
+}
+
+Layout make_layout(const dg_hgks_params& p, int max_stride) {
+  Layout L;
+  const int nq = p.nq ? p.nq : p.degree + 1;
+  (void)nq;
+  const size_t N = (size_t)p.nx * p.ny * p.nz;
+  const size_t nm = (size_t)dgk::nmodes(p.degree), nt = (size_t)dgk::ntan(p.degree);
+  const size_t Ts = p.precision == DG_HGKS_FP32_BULK ? 4 : 8;
+  const size_t state = 5 * nm * N;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.flag = take(kAlign);
+  L.qs = (Ts == 4) ? take(state * Ts) : 0;
+  L.qstar = take(state * Ts);
+  L.P = take(state * 8);
+  L.rec = take(3 * N * 10 * nt * Ts);
+  if (max_stride > 0) {
+    L.adj_states = take((size_t)max_stride * state * 8);  // Q^n of each step of a segment
+    L.adj_stars = take((size_t)max_stride * state * Ts);  // Q* of each step
+    L.adj_qbar = take(state * 8);
+    L.adj_qsbar = take(state * 8);
+    L.adj_Lbar = take(state * 8);
+    L.adj_Ltbar = take(state * 8);
+    L.adj_frec = take(3 * N * 2 * 5 * nm * 8);  // per face: cotangents of both cells' coefficients
+    L.adj_mu = take(adj_mu_slots(N) * 8);
+    L.adj_tmp = take(kAlign);
+  }
+  L.total = off;
+  return L;
+}
+
+Geo make_geo(const dg_hgks_params& p) {
+  Geo g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.ncell = (long long)p.nx * p.ny * p.nz;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int e = 0; e < 3; ++e) {
+    const double dx = (p.hi[e] - p.lo[e]) / n[e];
+    g.two_inv_dx[e] = 2.0 / dx;
+    g.inv_dx[e] = 1.0 / dx;
+  }
+  return g;
+}
+
+Phys make_phys(const dg_hgks_ctx* c, double dt) {
+  Phys ph{};
+  ph.K = (5.0 - 3.0 * c->p.gamma) / (c->p.gamma - 1.0);
+  ph.gm1 = c->p.gamma - 1.0;
+  ph.mu = c->mu;
+  ph.inv_pr_m1 = 1.0 / c->p.prandtl - 1.0;
+  ph.dt = dt;
+  return ph;
+}
+
+template <class T_, int K_, int NQ_>
+struct Tag {
+  using T = T_;
+  static constexpr int K = K_, NQ = NQ_;
+};
+
+template <class F>
+int dispatch(const dg_hgks_params& p, F&& f) {
+  const bool f32 = p.precision == DG_HGKS_FP32_BULK;
+  const int k = p.degree, nq = p.nq ? p.nq : p.degree + 1;
+  if (k == 1 && nq == 2) return f32 ? f(Tag<float, 1, 2>{}) : f(Tag<double, 1, 2>{});
+  if (k == 2 && nq == 3) return f32 ? f(Tag<float, 2, 3>{}) : f(Tag<double, 2, 3>{});
+  if (k == 2 && nq == 2) return f32 ? f(Tag<float, 2, 2>{}) : f(Tag<double, 2, 2>{});
+  return DG_HGKS_EUNSUPPORTED;
+}
+
+// ---- event timing -----------------------------------------------------------
+int t_begin(dg_hgks_ctx* c, int cls) {
+  if (!c->timing) return DG_HGKS_OK;
+  TimingRec r{cls, nullptr, nullptr};
+  DG_HIP(c, hipEventCreate(&r.a));
+  DG_HIP(c, hipEventCreate(&r.b));
+  DG_HIP(c, hipEventRecord(r.a, c->stream));
+  c->trecs.push_back(r);
+  return DG_HGKS_OK;
+}
+int t_end(dg_hgks_ctx* c) {
+  if (!c->timing) return DG_HGKS_OK;
+  DG_HIP(c, hipEventRecord(c->trecs.back().b, c->stream));
+  return DG_HGKS_OK;
+}
+int t_collect(dg_hgks_ctx* c) {
+  if (c->trecs.empty()) return DG_HGKS_OK;
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto& r : c->trecs) {
+    float ms = 0.f;
+    DG_HIP(c, hipEventElapsedTime(&ms, r.a, r.b));
+    c->t_ms[r.cls] += ms;
+    c->t_n[r.cls] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->trecs.clear();
+  return DG_HGKS_OK;
+}
+
+#define DG_LAUNCH(ctx, cls, ...)                  \
+  do {                                            \
+    int rc_ = t_begin(ctx, cls);                  \
+    if (rc_) return rc_;                          \
+    __VA_ARGS__;                                  \
+    DG_HIP(ctx, hipGetLastError());               \
+    rc_ = t_end(ctx);                             \
+    if (rc_) return rc_;                          \
+  } while (0)
+
+__global__ void clear_flag_kernel(int* f) {
+  if (threadIdx.x == 0) f[0] = 0;
+}
+
+int ensure_flag(dg_hgks_ctx* c) {
+  if (c->flag_ready) return DG_HGKS_OK;
+  clear_flag_kernel<<<1, 64, 0, c->stream>>>((int*)(c->ws + c->lay.flag));
+  DG_HIP(c, hipGetLastError());
+  c->flag_ready = true;
+  return DG_HGKS_OK;
+}
+
+template <class T>
+int launch_convert(dg_hgks_ctx* c, const double* a, T* b, long long n) {
+  const long long nb = std::min<long long>((n + 255) / 256, 65536);
+  DG_LAUNCH(c, 2, (convert_kernel<T><<<dim3((unsigned)nb), 256, 0, c->stream>>>(a, b, n)));
+  return DG_HGKS_OK;
+}
+
+// One operator evaluation (face pass + volume pass).
+template <class T, int K, int NQ, int MODE>
+int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g, const Phys& ph) {
+  using FC = FaceCfg<K, NQ>;
+  using VC = VolCfg<K, NQ>;
+  T* rec = (T*)(c->ws + c->lay.rec);
+  int* flag = (int*)(c->ws + c->lay.flag);
+  const long long N = g.ncell;
+  const unsigned bpd = (unsigned)((N + FC::FPB - 1) / FC::FPB);
+  const unsigned nvb = (unsigned)((N + VC::CPB - 1) / VC::CPB);
+  if constexpr (MODE == 1) {
+    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, rec, g, ph, flag)));
+  } else {
+    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, rec, g, ph, flag)));
+  }
+  DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE><<<dim3(nvb), VC::NTH, 0, c->stream>>>(qin, rec, g, ph, o, flag)));
+  return DG_HGKS_OK;
+}
+
+template <class T, int K, int NQ>
+int run_step(dg_hgks_ctx* c, double* q, double dt, int nsteps, double* ckpt, int stride) {
+  const Geo g = make_geo(c->p);
+  const Phys ph = make_phys(c, dt);
+  const long long n = 5LL * c->nm * g.ncell;
+  constexpr bool bulk = sizeof(T) == 4;
+  T* qs = bulk ? (T*)(c->ws + c->lay.qs) : nullptr;
+  T* qstar = (T*)(c->ws + c->lay.qstar);
+  double* P = (double*)(c->ws + c->lay.P);
+  int rc = ensure_flag(c);
+  if (rc) return rc;
+  if (bulk && nsteps > 0) {
+    rc = launch_convert<T>(c, q, qs, n);
+    if (rc) return rc;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    if (ckpt && s % stride == 0)
+      DG_HIP(c, hipMemcpyAsync(ckpt + (size_t)(s / stride) * n, q, n * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    const T* qin = bulk ? qs : (const T*)q;
+    VolOut<T> o1{};
+    o1.qn = q;
+    o1.P = P;
+    o1.qstar = qstar;
+    o1.dt = dt;
+    rc = launch_stage<T, K, NQ, 0>(c, qin, o1, g, ph);
+    if (rc) return rc;
+    VolOut<T> o2{};
+    o2.P = P;
+    o2.qnew = q;
+    o2.qshadow = qs;
+    o2.dt = dt;
+    rc = launch_stage<T, K, NQ, 1>(c, qstar, o2, g, ph);
+    if (rc) return rc;
+  }
+  return DG_HGKS_OK;
+}
+
+template <class T, int K, int NQ>
+int run_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* Lt) {
+  const Geo g = make_geo(c->p);
+  const Phys ph = make_phys(c, dt);
+  const long long n = 5LL * c->nm * g.ncell;
+  int rc = ensure_flag(c);
+  if (rc) return rc;
+  const T* qin;
+  if constexpr (sizeof(T) == 4) {
+    T* qs = (T*)(c->ws + c->lay.qs);
+    rc = launch_convert<T>(c, q, qs, n);
+    if (rc) return rc;
+    qin = qs;
+  } else {
+    qin = q;
+  }
+  VolOut<T> o{};
+  o.L = L;
+  o.Lt = Lt;
+  o.dt = dt;
+  return launch_stage<T, K, NQ, 2>(c, qin, o, g, ph);
+}
+
+template <class T, int K, int NQ>
+int run_adjoint(dg_hgks_ctx* c, const double*, int, double, int, const double*, double*, double*) {
+  return fail(c, DG_HGKS_EUNSUPPORTED, "adjoint not built");
+}
+
+}  // namespace
+
+// ============================================================================
+// C-ABI
+// ============================================================================
+extern "C" {
+
+int64_t dg_hgks_nmodes(int32_t degree) {
+  if (degree < 1 || degree > 3) return -1;
+  return dgk::nmodes(degree);
+}
+
+size_t dg_hgks_workspace_bytes(const dg_hgks_params* p, int32_t max_stride) {
+  std::string why;
+  if (validate(p, why) != DG_HGKS_OK || max_stride < 0) return 0;
+  return make_layout(*p, max_stride).total;
+}
+
+int dg_hgks_init(const dg_hgks_params* p, void* hip_stream, void* workspace, size_t workspace_bytes,
+                 dg_hgks_ctx** out) {
+  if (!out) return fail(nullptr, DG_HGKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  if (!workspace) return fail(nullptr, DG_HGKS_EINVAL, "workspace is NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(nullptr, DG_HGKS_EINVAL, "workspace must be 256-byte aligned");
+  // max_stride is derived from the workspace: the largest stride that fits
+  const Layout base = make_layout(*p, 0);
+  if (workspace_bytes < base.total) return fail(nullptr, DG_HGKS_ENOMEM, "workspace smaller than dg_hgks_workspace_bytes");
+  int ms = 0;
+  while (ms < (1 << 20) && make_layout(*p, ms + 1).total <= workspace_bytes) ++ms;
+  dg_hgks_ctx* c = new (std::nothrow) dg_hgks_ctx;
+  if (!c) return fail(nullptr, DG_HGKS_ENOMEM, "host allocation failed");
+  c->p = *p;
+  if (c->p.nq == 0) c->p.nq = c->p.degree + 1;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = workspace_bytes;
+  c->max_stride = ms;
+  c->lay = make_layout(c->p, ms);
+  c->ncell = (long long)p->nx * p->ny * p->nz;
+  c->nm = dgk::nmodes(p->degree);
+  c->nt = dgk::ntan(p->degree);
+  c->mu = p->mu;
+  *out = c;
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_step(dg_hgks_ctx* c, double* q, double dt, int32_t nsteps, double* ckpt, int32_t ckpt_stride) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!q) return fail(c, DG_HGKS_EINVAL, "q is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_HGKS_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(c, DG_HGKS_EINVAL, "nsteps must be >= 0");
+  if (ckpt && ckpt_stride < 1) return fail(c, DG_HGKS_EINVAL, "ckpt_stride must be >= 1");
+  return dispatch(c->p, [&](auto tag) {
+    using Tg = decltype(tag);
+    return run_step<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, nsteps, ckpt, ckpt_stride);
+  });
+}
+
+int dg_hgks_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* Lt) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!q || !L || !Lt) return fail(c, DG_HGKS_EINVAL, "NULL pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_HGKS_EINVAL, "dt must be finite and > 0");
+  return dispatch(c->p, [&](auto tag) {
+    using Tg = decltype(tag);
+    return run_residual<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, L, Lt);
+  });
+}
+
+int dg_hgks_adjoint(dg_hgks_ctx* c, const double* ckpt, int32_t ckpt_stride, double dt, int32_t nsteps,
+                    const double* qN_bar, double* q0_bar, double* mu_bar_host) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!ckpt || !qN_bar || !q0_bar || !mu_bar_host) return fail(c, DG_HGKS_EINVAL, "NULL pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_HGKS_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(c, DG_HGKS_EINVAL, "nsteps must be >= 0");
+  if (ckpt_stride < 1) return fail(c, DG_HGKS_EINVAL, "ckpt_stride must be >= 1");
+  if (ckpt_stride > c->max_stride)
+    return fail(c, DG_HGKS_ENOMEM, "ckpt_stride exceeds the adjoint room of the workspace");
+  return dispatch(c->p, [&](auto tag) {
+    using Tg = decltype(tag);
+    return run_adjoint<typename Tg::T, Tg::K, Tg::NQ>(c, ckpt, ckpt_stride, dt, nsteps, qN_bar, q0_bar,
+                                                       mu_bar_host);
+  });
+}
+
+int dg_hgks_set_mu(dg_hgks_ctx* c, double mu) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(c, DG_HGKS_EINVAL, "mu must be >= 0");
+  c->mu = mu;
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_set_stream(dg_hgks_ctx* c, void* hip_stream) {
+  if (!c) return DG_HGKS_EINVAL;
+  c->stream = (hipStream_t)hip_stream;
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_check(dg_hgks_ctx* c) {
+  if (!c) return DG_HGKS_EINVAL;
+  int rc = ensure_flag(c);
+  if (rc) return rc;
+  int h = 0;
+  int* f = (int*)(c->ws + c->lay.flag);
+  DG_HIP(c, hipMemcpyAsync(&h, f, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  DG_HIP(c, hipStreamSynchronize(c->stream));
+  if (h) {
+    clear_flag_kernel<<<1, 64, 0, c->stream>>>(f);
+    DG_HIP(c, hipGetLastError());
+    return fail(c, DG_HGKS_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or non-finite) met");
+  }
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_point_face_flux(dg_hgks_ctx* c, const double* x, int64_t n, int32_t axis, double dt, double* F,
+                            double* Ft) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!x || !F || !Ft || n < 0 || axis < 0 || axis > 2 || !(dt > 0.0)) return fail(c, DG_HGKS_EINVAL, "bad argument");
+  if (n == 0) return DG_HGKS_OK;
+  int rc = ensure_flag(c);
+  if (rc) return rc;
+  const Phys ph = make_phys(c, dt);
+  int* flag = (int*)(c->ws + c->lay.flag);
+  const unsigned nb = (unsigned)((n + 63) / 64);
+  if (c->p.precision == DG_HGKS_FP32_BULK)
+    DG_LAUNCH(c, 0, (point_face_kernel<float><<<nb, 64, 0, c->stream>>>(x, F, Ft, n, axis, ph, flag)));
+  else
+    DG_LAUNCH(c, 0, (point_face_kernel<double><<<nb, 64, 0, c->stream>>>(x, F, Ft, n, axis, ph, flag)));
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_point_volume_flux(dg_hgks_ctx* c, const double* x, int64_t n, double* F, double* Ft) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!x || !F || !Ft || n < 0) return fail(c, DG_HGKS_EINVAL, "bad argument");
+  if (n == 0) return DG_HGKS_OK;
+  int rc = ensure_flag(c);
+  if (rc) return rc;
+  const Phys ph = make_phys(c, 1.0);
+  int* flag = (int*)(c->ws + c->lay.flag);
+  const unsigned nb = (unsigned)((n + 63) / 64);
+  if (c->p.precision == DG_HGKS_FP32_BULK)
+    DG_LAUNCH(c, 1, (point_volume_kernel<float><<<nb, 64, 0, c->stream>>>(x, F, Ft, n, ph, flag)));
+  else
+    DG_LAUNCH(c, 1, (point_volume_kernel<double><<<nb, 64, 0, c->stream>>>(x, F, Ft, n, ph, flag)));
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_set_timing(dg_hgks_ctx* c, int32_t enable) {
+  if (!c) return DG_HGKS_EINVAL;
+  int rc = t_collect(c);
+  if (rc) return rc;
+  for (int i = 0; i < 5; ++i) {
+    c->t_ms[i] = 0;
+    c->t_n[i] = 0;
+  }
+  c->timing = enable != 0;
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_get_timing(dg_hgks_ctx* c, double* ms, int64_t* counts, int32_t n) {
+  if (!c) return DG_HGKS_EINVAL;
+  int rc = t_collect(c);
+  if (rc) return rc;
+  for (int i = 0; i < n && i < 5; ++i) {
+    if (ms) ms[i] = c->t_ms[i];
+    if (counts) counts[i] = c->t_n[i];
+  }
+  return 5;
+}
+
+const char* dg_hgks_last_error(const dg_hgks_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+const char* dg_hgks_strerror(int s) {
+  switch (s) {
+    case DG_HGKS_OK: return "ok";
+    case DG_HGKS_EINVAL: return "invalid argument";
+    case DG_HGKS_ENOMEM: return "workspace too small";
+    case DG_HGKS_EHIP: return "HIP runtime error";
+    case DG_HGKS_ENONPHYS: return "non-physical state";
+    case DG_HGKS_EUNSUPPORTED: return "unsupported (degree, nq)";
+    default: return "unknown status";
+  }
+}
+
+int dg_hgks_destroy(dg_hgks_ctx* c) {
+  if (!c) return DG_HGKS_EINVAL;
+  for (auto& r : c->trecs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  delete c;
+  return DG_HGKS_OK;
+}
+
+}  // extern "C"

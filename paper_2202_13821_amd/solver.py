@@ -1,0 +1,211 @@
+"""Python front end of the C-ABI: a Solver bound to one HIP stream, and a
+torch.autograd.Function around the forward step and its hand-written adjoint.
+
+torch provides device memory and the stream; every operation of the method
+runs in libdg_hgks.so.
+"""
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from .problems import nmodes
+
+PRECISIONS = {"fp64": _lib.DG_HGKS_FP64, "fp32_bulk": _lib.DG_HGKS_FP32_BULK}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One DG-HGKS discretisation on a periodic box.
+
+    q tensors: float64, shape (5, nmodes, nz, ny, nx), contiguous, on `device`.
+    """
+
+    def __init__(self, shape, lo, hi, degree, nq=0, gamma=1.4, mu=0.0, prandtl=1.0, precision="fp64",
+                 device="cuda", max_stride=0):
+        self.lib = _lib.load()
+        self.shape = tuple(int(s) for s in shape)
+        self.lo, self.hi = tuple(lo), tuple(hi)
+        self.degree = int(degree)
+        self.nq = int(nq) if nq else self.degree + 1
+        self.gamma, self.prandtl = float(gamma), float(prandtl)
+        self._mu = float(mu)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.params = _lib.make_params(self.shape, lo, hi, degree, nq, gamma, mu, prandtl, PRECISIONS[precision])
+        nbytes = self.lib.dg_hgks_workspace_bytes(ctypes.byref(self.params), int(max_stride))
+        if nbytes == 0:
+            raise _lib.DGHGKSError(_lib.DG_HGKS_EINVAL, "invalid parameters")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.dg_hgks_init(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                                   _ptr(self.workspace), int(nbytes), ctypes.byref(ctx))
+        _lib.check(rc, None)
+        self.ctx = ctx
+        self.max_stride = int(max_stride)
+
+    # -- helpers -------------------------------------------------------------
+    @property
+    def field_shape(self):
+        nx, ny, nz = self.shape
+        return (5, nmodes(self.degree), nz, ny, nx)
+
+    @property
+    def mu(self):
+        return self._mu
+
+    def _chk(self, rc):
+        return _lib.check(rc, self.ctx)
+
+    def _field(self, q, name="q"):
+        if q.dtype != torch.float64 or q.device != self.device or not q.is_contiguous() \
+                or tuple(q.shape) != self.field_shape:
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {self.field_shape} on "
+                             f"{self.device}")
+        return q
+
+    # -- C-ABI calls -----------------------------------------------------------
+    def set_mu(self, mu):
+        self._chk(self.lib.dg_hgks_set_mu(self.ctx, float(mu)))
+        self._mu = float(mu)
+
+    def step(self, q, dt, nsteps=1, ckpt=None, ckpt_stride=0):
+        """Advance q in place by nsteps S2O4 steps."""
+        self._field(q)
+        cp = _ptr(ckpt) if ckpt is not None else None
+        self._chk(self.lib.dg_hgks_step(self.ctx, _ptr(q), float(dt), int(nsteps), cp, int(ckpt_stride)))
+        return q
+
+    def residual(self, q, dt):
+        self._field(q)
+        L = torch.empty_like(q)
+        Lt = torch.empty_like(q)
+        self._chk(self.lib.dg_hgks_residual(self.ctx, _ptr(q), float(dt), _ptr(L), _ptr(Lt)))
+        return L, Lt
+
+    def adjoint(self, ckpt, ckpt_stride, dt, nsteps, qN_bar):
+        """Returns (q0_bar, mu_bar)."""
+        self._field(qN_bar, "qN_bar")
+        q0_bar = torch.empty_like(qN_bar)
+        mu_bar = ctypes.c_double()
+        self._chk(self.lib.dg_hgks_adjoint(self.ctx, _ptr(ckpt), int(ckpt_stride), float(dt), int(nsteps),
+                                           _ptr(qN_bar), _ptr(q0_bar), ctypes.byref(mu_bar)))
+        return q0_bar, mu_bar.value
+
+    def check(self):
+        self._chk(self.lib.dg_hgks_check(self.ctx))
+
+    def point_face_flux(self, x, axis, dt):
+        x = x.contiguous()
+        n = x.shape[0]
+        F = torch.empty((n, 5), dtype=torch.float64, device=self.device)
+        Ft = torch.empty_like(F)
+        self._chk(self.lib.dg_hgks_point_face_flux(self.ctx, _ptr(x), n, int(axis), float(dt), _ptr(F), _ptr(Ft)))
+        return F, Ft
+
+    def point_volume_flux(self, x):
+        x = x.contiguous()
+        n = x.shape[0]
+        F = torch.empty((n, 3, 5), dtype=torch.float64, device=self.device)
+        Ft = torch.empty_like(F)
+        self._chk(self.lib.dg_hgks_point_volume_flux(self.ctx, _ptr(x), n, _ptr(F), _ptr(Ft)))
+        return F, Ft
+
+    def set_timing(self, enable=True):
+        self._chk(self.lib.dg_hgks_set_timing(self.ctx, 1 if enable else 0))
+
+    def get_timing(self):
+        """{'face': (ms, launches), 'volume': ..., 'convert': ..., 'adj_face': ..., 'adj_volume': ...}"""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int64 * 5)()
+        rc = self.lib.dg_hgks_get_timing(self.ctx, ms, cnt, 5)
+        if rc < 0:
+            self._chk(rc)
+        names = ["face", "volume", "convert", "adj_face", "adj_volume"]
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.dg_hgks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- time integration with checkpoints -------------------------------------
+    def checkpoint_stride(self, nsteps):
+        return max(1, int(math.ceil(math.sqrt(nsteps))))
+
+    def new_checkpoints(self, nsteps, stride):
+        nslots = (nsteps + stride - 1) // stride
+        return torch.empty((max(nslots, 1),) + self.field_shape, dtype=torch.float64, device=self.device)
+
+
+def kinetic_energy(q, solver):
+    """Domain-integrated kinetic energy J = sum_K |K| sum_q w_q |rho U|^2/(2 rho)
+    on the volume Gauss rule of the solver (differentiable torch expression,
+    evaluated with the same basis tables as problems.modes)."""
+    import numpy as np
+
+    from .problems import modes
+
+    nq = solver.nq
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    wg = wg / 2.0
+    md = modes(solver.degree)
+    leg = lambda l, x: np.polynomial.legendre.legval(x, [0.0] * l + [1.0])
+    # B[n][gz][gy][gx]
+    B = np.zeros((len(md), nq, nq, nq))
+    for n, (a, b, c) in enumerate(md):
+        B[n] = leg(c, xg)[:, None, None] * leg(b, xg)[None, :, None] * leg(a, xg)[None, None, :]
+    W = wg[:, None, None] * wg[None, :, None] * wg[None, None, :]
+    Bt = torch.as_tensor(B, dtype=q.dtype, device=q.device)
+    Wt = torch.as_tensor(W, dtype=q.dtype, device=q.device)
+    vals = torch.einsum("vnkji,nabc->vkjiabc", q[:4], Bt)
+    rho = vals[0]
+    ke = (vals[1] ** 2 + vals[2] ** 2 + vals[3] ** 2) / (2.0 * rho)
+    nx, ny, nz = solver.shape
+    vol = 1.0
+    for e, n in enumerate((nx, ny, nz)):
+        vol *= (solver.hi[e] - solver.lo[e]) / n
+    return (ke * Wt).sum() * vol
+
+
+class DGHGKSSteps(torch.autograd.Function):
+    """q_N = S2O4^n(q_0; mu) with gradients from the hand-written adjoint.
+
+    forward(q0, mu_tensor, solver, dt, nsteps) stores sqrt(n)-spaced
+    checkpoints; backward recomputes each segment and runs the adjoint.
+    """
+
+    @staticmethod
+    def forward(ctx, q0, mu, solver, dt, nsteps):
+        solver.set_mu(float(mu.item()))
+        stride = solver.checkpoint_stride(nsteps)
+        if stride > solver.max_stride:
+            raise ValueError(f"solver built with max_stride={solver.max_stride} < {stride}")
+        ckpt = solver.new_checkpoints(nsteps, stride)
+        q = q0.detach().clone().contiguous()
+        solver.step(q, dt, nsteps, ckpt, stride)
+        ctx.solver, ctx.dt, ctx.nsteps, ctx.stride = solver, dt, nsteps, stride
+        ctx.save_for_backward(ckpt)
+        return q
+
+    @staticmethod
+    def backward(ctx, gq):
+        (ckpt,) = ctx.saved_tensors
+        q0_bar, mu_bar = ctx.solver.adjoint(ckpt, ctx.stride, ctx.dt, ctx.nsteps, gq.contiguous())
+        mu_grad = torch.tensor(mu_bar, dtype=torch.float64, device=gq.device)
+        return q0_bar, mu_grad, None, None, None
+
+
+def steps(q0, mu, solver, dt, nsteps):
+    return DGHGKSSteps.apply(q0, mu, solver, dt, nsteps)

@@ -1,0 +1,276 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+FP64 path: relative L2 <= 1e-10 on every step test (1e-12 for one operator
+evaluation, 1e-12 relative for point fluxes).  FP32-bulk path: the
+tolerances below are the ones stated for it (float32 rounding of point
+values and fluxes at the given Mach number, accumulated in FP64).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import inputs as IN
+import oracle as O
+from gpu_util import pair, rel_l2, rel_l2_groups, rel_max, say, to_dev, to_np
+from paper_2202_13821_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+TGV_LO, TGV_HI = (-math.pi,) * 3, (math.pi,) * 3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    say("device:", torch.cuda.get_device_name(0))
+
+
+# ---------------------------------------------------------------------------
+# point fluxes
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_bulk", 2e-5)])
+@pytest.mark.parametrize("mu,pr", [(0.0, 1.0), (1e-4, 0.72), (1 / 1600, 0.72), (0.05, 0.72)])
+def test_point_volume_flux(precision, tol, mu, pr):
+    say("point volume", precision, mu, pr)
+    rng = np.random.default_rng(100)
+    s, c = pair((1, 1, 1), 2, (0, 0, 0), (1, 1, 1), mu=mu, pr=pr, precision=precision)
+    X, ref_F, ref_Ft = [], [], []
+    for lm in (False, True):
+        for _ in range(32):
+            q, dq = IN.point_state(rng, lm), IN.point_gradient(rng)
+            F, Ft = O.volume_flux(c, q, dq)
+            X.append(np.concatenate([q, dq.ravel()]))
+            ref_F.append(F)
+            ref_Ft.append(Ft)
+    F, Ft = s.point_volume_flux(to_dev(np.array(X)))
+    F, Ft = to_np(F), to_np(Ft)
+    for i in range(len(X)):
+        assert rel_max(F[i], ref_F[i]) <= tol, (i, F[i], ref_F[i])
+        assert rel_max(Ft[i], ref_Ft[i]) <= tol * (100 if precision != "fp64" else 10), (i,)
+    s.check()
+
+
+@pytest.mark.parametrize("precision,tol,tolt", [("fp64", 1e-12, 1e-10), ("fp32_bulk", 2e-5, 2e-2)])
+@pytest.mark.parametrize("mu,pr,dt", [(0.0, 1.0, 1e-2), (1e-4, 0.72, 1e-2), (1 / 1600, 0.72, 6.67782e-4),
+                                      (0.05, 0.72, 1e-3)])
+def test_point_face_flux(precision, tol, tolt, mu, pr, dt):
+    say("point face", precision, mu, pr, dt)
+    rng = np.random.default_rng(200)
+    s, c = pair((1, 1, 1), 2, (0, 0, 0), (1, 1, 1), mu=mu, pr=pr, precision=precision)
+    for d in range(3):
+        X, ref = [], []
+        for lm in (False, True):
+            for _ in range(32):
+                qL = IN.point_state(rng, lm)
+                qR = qL + rng.normal(0, 0.05, 5) * np.abs(qL) if rng.uniform() < 0.5 else IN.point_state(rng, lm)
+                dqL, dqR = IN.point_gradient(rng), IN.point_gradient(rng)
+                ref.append(O.face_flux(c, dt, d, qL, dqL, qR, dqR))
+                X.append(np.concatenate([qL, dqL.ravel(), qR, dqR.ravel()]))
+        F, Ft = s.point_face_flux(to_dev(np.array(X)), d, dt)
+        F, Ft = to_np(F), to_np(Ft)
+        for i in range(len(X)):
+            assert rel_max(F[i], ref[i][0]) <= tol, (d, i, F[i], ref[i][0])
+            # Ft is a difference quotient of time integrals (cancellation ~ 1/(dt |F_t|/|F|))
+            scale = max(np.abs(ref[i][1]).max(), np.abs(ref[i][0]).max() / dt * 1e-3)
+            assert np.abs(Ft[i] - ref[i][1]).max() <= tolt * scale, (d, i, Ft[i], ref[i][1])
+    s.check()
+
+
+# ---------------------------------------------------------------------------
+# operator L, L_t
+# ---------------------------------------------------------------------------
+RESIDUAL_CASES = [
+    # shape, k, nq, problem, mu, pr
+    ((4, 4, 4), 1, 2, "random", 0.01, 0.72),
+    ((5, 6, 7), 2, 3, "random", 0.01, 0.72),
+    ((8, 8, 8), 2, 3, "tgv", 1 / 1600, 0.72),
+    ((3, 1, 2), 2, 3, "random", 0.0, 1.0),
+    ((29, 3, 2), 2, 3, "random", 0.02, 0.72),
+    ((6, 5, 4), 2, 2, "random", 0.01, 0.72),
+]
+
+
+def _field(shape, k, problem, rng, low_mach=False):
+    if problem == "tgv":
+        q, lo, hi = P.tgv(shape, k)
+        return q, lo, hi
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.3, 0.7)
+    return IN.random_field(rng, shape, P.nmodes(k), amp=0.03, low_mach=low_mach), lo, hi
+
+
+@pytest.mark.parametrize("shape,k,nq,problem,mu,pr", RESIDUAL_CASES)
+def test_residual_fp64(shape, k, nq, problem, mu, pr):
+    say("residual fp64", shape, k, nq, problem)
+    rng = np.random.default_rng(300)
+    q, lo, hi = _field(shape, k, problem, rng)
+    s, c = pair(shape, k, lo, hi, nq=nq, mu=mu, pr=pr)
+    dt = 3e-3
+    L, Lt = s.residual(to_dev(q), dt)
+    Lo, Lto = O.residual(c, q, dt)
+    eL, eLt = rel_l2_groups(to_np(L), Lo), rel_l2_groups(to_np(Lt), Lto)
+    say("  rel L2 of L, Lt:", eL, eLt)
+    # FP64 rounding, amplified by the cancellation of O(p) fluxes at low Mach
+    assert eL <= 1e-11 and eLt <= 1e-10
+    s.check()
+
+
+@pytest.mark.parametrize("shape,k,nq,problem,mu,pr", RESIDUAL_CASES[:4])
+def test_residual_fp32_bulk(shape, k, nq, problem, mu, pr):
+    say("residual fp32", shape, k, nq, problem)
+    rng = np.random.default_rng(301)
+    q, lo, hi = _field(shape, k, problem, rng)
+    s, c = pair(shape, k, lo, hi, nq=nq, mu=mu, pr=pr, precision="fp32_bulk")
+    dt = 3e-3
+    L, Lt = s.residual(to_dev(q), dt)
+    Lo, Lto = O.residual(c, q, dt)
+    eL, eLt = rel_l2_groups(to_np(L), Lo), rel_l2_groups(to_np(Lt), Lto)
+    say("  rel L2 of L, Lt:", eL, eLt)
+    # float32 point values and fluxes; the operator is a difference of O(p)
+    # fluxes, so its relative error grows like eps32 * p / |L| at low Mach
+    tol = 5e-3 if problem == "tgv" else 1e-4
+    assert eL <= tol and eLt <= 10 * tol
+
+
+# ---------------------------------------------------------------------------
+# full steps
+# ---------------------------------------------------------------------------
+def test_step_c1_advection_p1_fp64():
+    """8^3 P1 advection, 2x2x2 / 2x2 points, 10 steps at CFL 0.1."""
+    say("C1")
+    shape = (8, 8, 8)
+    q0, lo, hi = P.advection(shape, 1)
+    s, c = pair(shape, 1, lo, hi)
+    dt = P.advection_dt(8)
+    q = to_dev(q0)
+    s.step(q, dt, 10)
+    qo = O.step(c, q0, dt, 10)
+    assert rel_l2(to_np(q), qo) <= 1e-10
+    s.check()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32_bulk", 1e-5)])
+def test_step_tgv_8(precision, tol):
+    say("tgv8", precision)
+    shape = (8, 8, 8)
+    q0, lo, hi = P.tgv(shape, 2)
+    s, c = pair(shape, 2, lo, hi, mu=1 / 1600, pr=0.72, precision=precision)
+    dt = P.tgv_dt(8)
+    q = to_dev(q0)
+    s.step(q, dt, 3)
+    qo = O.step(c, q0, dt, 3)
+    e, ed = rel_l2_groups(to_np(q), qo), rel_l2_groups(to_np(q) - q0, qo - q0)
+    say("  rel L2 of q, of q - q0:", e, ed, "per variable:", [rel_l2(to_np(q)[v:v+1].repeat(5, 0), qo[v:v+1].repeat(5, 0)) for v in range(5)])
+    assert e <= tol
+    # the change over the steps is matched too (not only the large background)
+    assert ed <= (1e-9 if precision == "fp64" else 5e-2)
+
+
+def test_step_random_ragged_fp64():
+    say("ragged")
+    rng = np.random.default_rng(400)
+    shape = (7, 5, 3)
+    q0 = IN.random_field(rng, shape, 10, amp=0.03)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 0.8, 0.6)
+    s, c = pair(shape, 2, lo, hi, mu=0.005, pr=0.72)
+    q = to_dev(q0)
+    s.step(q, 2e-3, 2)
+    qo = O.step(c, q0, 2e-3, 2)
+    assert rel_l2(to_np(q) - q0, qo - q0) <= 1e-9
+    assert rel_l2(to_np(q), qo) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_step_full_size_tgv128_sampled(precision):
+    """128^3 P2 Taylor-Green, the benchmark configuration and launch shape:
+    one step on the GPU, Q^{n+1} of sampled cells from the oracle."""
+    say("tgv128 sampled", precision)
+    shape = (128, 128, 128)
+    q0, lo, hi = P.tgv(shape, 2)
+    s, c = pair(shape, 2, lo, hi, mu=1 / 1600, pr=0.72, precision=precision)
+    dt = P.tgv_dt(128)
+    q = to_dev(q0)
+    s.step(q, dt, 1)
+    qg = to_np(q).reshape(5, 10, -1)
+    rng = np.random.default_rng(500)
+    N = 128 ** 3
+    cells = np.concatenate([[0, N - 1, 127, 128 * 127, N - 128 * 128], rng.integers(0, N, 11)])
+    ref = O.step_cells(c, q0, dt, cells)
+    # scale of each quantity over the samples: rho, momentum (one scale for the vector), rho E
+    scale = [np.abs(ref[:, 0]).max()] + [np.abs(ref[:, 1:4]).max()] * 3 + [np.abs(ref[:, 4]).max()]
+    worst = 0.0
+    for t, cc in enumerate(cells):
+        for v in range(5):
+            worst = max(worst, np.abs(qg[v, :, cc] - ref[t, v]).max() / scale[v])
+    say("  max sampled error / quantity scale:", worst)
+    assert worst <= (1e-13 if precision == "fp64" else 1e-5)
+    s.check()
+
+
+# ---------------------------------------------------------------------------
+# invariants on the GPU path
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_gpu_conservation_and_free_stream(precision):
+    say("conservation", precision)
+    rng = np.random.default_rng(600)
+    shape = (6, 5, 4)
+    q0 = IN.random_field(rng, shape, 10, amp=0.03)
+    s, _ = pair(shape, 2, (0, 0, 0), (1, 1, 1), mu=0.01, pr=0.72, precision=precision)
+    q = to_dev(q0)
+    s.step(q, 2e-3, 5)
+    tot0 = q0[:, 0].sum(axis=(1, 2, 3))
+    tot1 = to_np(q)[:, 0].sum(axis=(1, 2, 3))
+    tol = 1e-13 if precision == "fp64" else 1e-7
+    assert np.all(np.abs(tot1 - tot0) <= tol * np.abs(tot0).max())
+    qu = np.zeros_like(q0)
+    qu[:, 0] = np.array([1.1, 0.2, -0.3, 0.4, 2.9])[:, None, None, None]
+    q = to_dev(qu)
+    s.step(q, 2e-3, 5)
+    assert np.abs(to_np(q) - qu).max() <= (1e-13 if precision == "fp64" else 1e-6)
+
+
+def test_gpu_convergence_order_p2():
+    """Section 5.1 3-D advection to t = 0.5, P2: L2 error order ~ 3."""
+    say("order p2")
+    errs = []
+    for n in (8, 16, 32):
+        q0, lo, hi = P.advection((n, n, n), 2)
+        s, c = pair((n, n, n), 2, lo, hi)
+        dt0 = P.advection_dt(n)
+        nst = int(math.ceil(0.5 / dt0))
+        q = to_dev(q0)
+        s.step(q, 0.5 / nst, nst)
+        errs.append(O.advection_error(c, to_np(q), 0.5))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    say("errors", errs, "orders", orders)
+    assert np.all(np.abs(orders - 3.0) < 0.3)
+
+
+def test_gpu_deterministic():
+    say("determinism")
+    q0, lo, hi = P.tgv((16, 16, 16), 2)
+    s, _ = pair((16, 16, 16), 2, lo, hi, mu=1 / 1600, pr=0.72, precision="fp32_bulk")
+    a, b = to_dev(q0), to_dev(q0)
+    s.step(a, P.tgv_dt(16), 4)
+    s.step(b, P.tgv_dt(16), 4)
+    assert torch.equal(a, b)
+
+
+def test_nonphysical_flag_is_reported():
+    """A negative-pressure input is flagged (kernels still run to completion)."""
+    say("nonphysical")
+    shape = (4, 4, 4)
+    q0 = np.zeros((5, 10) + shape[::-1])
+    q0[0, 0] = 1.0
+    q0[4, 0] = -1.0  # negative internal energy
+    s, _ = pair(shape, 2, (0, 0, 0), (1, 1, 1))
+    q = to_dev(q0)
+    s.step(q, 1e-3, 1)
+    from paper_2202_13821_amd._lib import DGHGKSError, DG_HGKS_ENONPHYS
+
+    with pytest.raises(DGHGKSError) as e:
+        s.check()
+    assert e.value.status == DG_HGKS_ENONPHYS
+    s.check()  # flag cleared

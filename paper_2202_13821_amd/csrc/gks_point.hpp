@@ -44,6 +44,23 @@ DGK_HD float d_exp(float x) { return expf(x); }
 DGK_HD double d_exp(double x) { return exp(x); }
 DGK_HD float d_sqrt(float x) { return sqrtf(x); }
 DGK_HD double d_sqrt(double x) { return sqrt(x); }
+// Reciprocal, reciprocal square root and exp: FP32-bulk uses the hardware
+// instructions (v_rcp_f32, v_rsq_f32: 1 ulp; v_exp_f32: ~1-2 ulp), the FP64
+// path keeps IEEE-rounded division, sqrt and the library exp.
+#ifdef __HIP_DEVICE_COMPILE__
+DGK_HD float d_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+DGK_HD float d_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+DGK_HD float d_expf_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f); }
+#else
+DGK_HD float d_rcp(float x) { return 1.0f / x; }
+DGK_HD float d_rsqrt(float x) { return 1.0f / sqrtf(x); }
+DGK_HD float d_expf_fast(float x) { return expf(x); }
+#endif
+DGK_HD double d_rcp(double x) { return 1.0 / x; }
+DGK_HD double d_rsqrt(double x) { return 1.0 / sqrt(x); }
+DGK_HD float d_exp_bulk(float x) { return d_expf_fast(x); }
+DGK_HD double d_exp_bulk(double x) { return exp(x); }
+
 // x - x is 0 for every finite x and NaN for +-inf and NaN
 DGK_HD bool d_finite(float x) { return (x - x) == 0.0f; }
 DGK_HD bool d_finite(double x) { return (x - x) == 0.0; }
@@ -55,18 +72,24 @@ struct Phys {
   double mu;         // dynamic viscosity; tau = mu / p
   double inv_pr_m1;  // 1/Pr - 1 (Prandtl correction of the heat flux)
   double dt;         // time step (window of the time fit)
+  // derived on the host
+  double inv_k3;     // 1 / (K + 3)
+  double cp;         // (K + 5) / 2, heat capacity at constant pressure (R = 1)
+  double half_dt_over_mu;  // dt / (2 mu), 0 when mu = 0 (tau = 0)
+  double inv_dt;     // 1 / dt
 };
 
 template <class T>
 struct Prim {
-  T rho, U, V, W, th, p;  // th = p / rho = 1 / (2 lambda)
+  T rho, ir, U, V, W, th, p;  // ir = 1/rho, th = p / rho = 1 / (2 lambda)
 };
 
 template <class T>
 DGK_HD Prim<T> primitive(const T Q[5], T gm1) {
   Prim<T> s;
   s.rho = Q[0];
-  const T ir = T(1) / Q[0];
+  const T ir = d_rcp(Q[0]);
+  s.ir = ir;
   s.U = Q[1] * ir;
   s.V = Q[2] * ir;
   s.W = Q[3] * ir;
@@ -99,9 +122,10 @@ DGK_HD void mom_full(T U, T th, T* m) {
 // Gaussian at u = 0, then the same recurrence.
 template <class T>
 DGK_HD void mom_half(T U, T th, int side, T* m) {
-  const T r = T(1) / d_sqrt(T(2) * th);  // sqrt(lambda)
+  const T r = d_rsqrt(T(2) * th);  // sqrt(lambda)
   const T a = U * r;
-  const T e = d_exp(-a * a) * d_sqrt(th * T(0.15915494309189533577));  // sqrt(th / (2 pi))
+  // exp(-lambda U^2) / (2 sqrt(pi lambda)) = exp(-a^2) th r / sqrt(pi)
+  const T e = d_exp_bulk(-a * a) * (th * r * T(0.56418958354775628695));
   if (side > 0) {
     m[0] = T(0.5) * d_erfc(-a);
     m[1] = U * m[0] + e;
@@ -186,13 +210,13 @@ DGK_HD void psim(const Mom<T>& t, T out[5]) {
 template <class T>
 struct Solver5 {
   T U, V, W, ith, E, c4;
-  DGK_HD Solver5(const Prim<T>& s, T K) {
+  DGK_HD Solver5(const Prim<T>& s, T K, T inv_k3) {
     U = s.U;
     V = s.V;
     W = s.W;
-    ith = T(1) / s.th;
+    ith = d_rcp(s.th);
     E = T(0.5) * (U * U + V * V + W * W) + T(0.5) * (K + T(3)) * s.th;
-    c4 = T(2) * ith * ith / (K + T(3));
+    c4 = T(2) * ith * ith * inv_k3;
   }
   DGK_HD void operator()(const T b[5], T a[5]) const {
     const T R1 = b[1] - U * b[0], R2 = b[2] - V * b[0], R3 = b[3] - W * b[0];
@@ -212,8 +236,9 @@ struct Solver5 {
 // (c5, c6 enter with a minus sign).  The fit F dt + Ft dt^2/2 = FF(dt),
 // F dt/2 + Ft dt^2/8 = FF(dt/2) gives F = sum alpha_i m_i, Ft = sum beta_i m_i.
 // tau = 0 is the inviscid limit (e = 0): F = m1, Ft = m3.
-DGK_HD void time_coefficients(double tau, double dt, double alpha[6], double beta[6]) {
-  const double e2 = tau > 0.0 ? exp(-0.5 * dt / tau) : 0.0;
+// x_half = dt / (2 tau) (0 when tau = 0), inv_dt = 1 / dt.
+DGK_HD void time_coefficients(double tau, double x_half, double dt, double inv_dt, double alpha[6], double beta[6]) {
+  const double e2 = tau > 0.0 ? exp(-x_half) : 0.0;
   const double e1 = e2 * e2;
   double c[2][6];
   const double dl[2] = {dt, 0.5 * dt};
@@ -228,7 +253,7 @@ DGK_HD void time_coefficients(double tau, double dt, double alpha[6], double bet
     c[j][4] = -(2.0 * tau * tau - tau * (2.0 * tau + d) * e);
     c[j][5] = -(tau * tau * om);
   }
-  const double idt = 1.0 / dt, idt2 = 4.0 * idt * idt;
+  const double idt = inv_dt, idt2 = 4.0 * idt * idt;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     alpha[i] = (4.0 * c[1][i] - c[0][i]) * idt;
@@ -237,226 +262,256 @@ DGK_HD void time_coefficients(double tau, double dt, double alpha[6], double bet
 }
 
 // --------------------------------------------------------------------------
-// Face flux in the local frame: qL, dqL (trace of the lower cell, u > 0 half
-// space) and qR, dqR (upper cell, u < 0), dq*[i] = derivative along local
-// direction i (0 normal, 1 and 2 tangential).  Outputs F, Ft in the local frame.
-// NEED_F = false computes only Ft (second stage of S2O4).
+// Identities of Maxwellian moments used below (exact; with F_d(Q) =
+// rho <u_d psi> the Euler flux, J_d = dF_d/dQ):
+//  (i)   rho <u_d a psi> = J_d(Q) rho <a psi> for any slope a (first variation
+//        of the Maxwellian), hence the compatibility condition gives
+//        rho <A psi> = -sum_e J_e(Q) dQ/dx_e (the Euler time derivative) and
+//        rho <u_d A psi> = J_d(Q) rho <A psi>;
+//  (ii)  rho <u_d X psi> with X = sum_e u_e a_e + A equals
+//        p (0, D_d1, D_d2, D_d3, U.D_d + c_p dT/dx_d), where
+//        D_dj = dU_j/dx_d + dU_d/dx_j - 2/(K+3) delta_dj div U, c_p = (K+5)/2,
+//        T = p/rho (the Chapman-Enskog Navier-Stokes flux of BGK).
 // --------------------------------------------------------------------------
-template <class T, bool NEED_F>
-DGK_HD void face_flux_local(const Phys& ph, const T qL[5], const T dqL[3][5], const T qR[5], const T dqR[3][5],
-                            T F[5], T Ft[5], int& bad) {
+template <class T>
+struct Grad {
+  T dU[3][3];  // dU[e][j] = dU_j/dx_e
+  T dp[3], dT[3];
+};
+
+template <class T>
+DGK_HD Grad<T> prim_grad(const Prim<T>& s, const T dq[3][5], T gm1) {
+  Grad<T> g;
+  const T ir = s.ir;
+  const T U[3] = {s.U, s.V, s.W};
+  const T ke = T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    T um = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      g.dU[e][j] = (dq[e][1 + j] - U[j] * dq[e][0]) * ir;
+      um += U[j] * dq[e][1 + j];
+    }
+    g.dp[e] = gm1 * (dq[e][4] - um + ke * dq[e][0]);
+    g.dT[e] = (g.dp[e] - s.th * dq[e][0]) * ir;
+  }
+  return g;
+}
+
+// Euler flux along axis D of the (local or global) frame.
+template <int D, class T>
+DGK_HD void euler_flux(const Prim<T>& s, const T Q[5], T F[5]) {
+  const T U[3] = {s.U, s.V, s.W};
+  const T Ud = U[D];
+  F[0] = Q[1 + D];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) F[1 + j] = Q[1 + j] * Ud;
+  F[1 + D] += s.p;
+  F[4] = (Q[4] + s.p) * Ud;
+}
+
+// J_D(Q) v, the directional derivative of the Euler flux along axis D.
+template <int D, class T>
+DGK_HD void euler_jvp(const Prim<T>& s, const T Q[5], T gm1, const T v[5], T out[5]) {
+  const T U[3] = {s.U, s.V, s.W};
+  const T ir = s.ir;
+  T dU[3], um = T(0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    dU[j] = (v[1 + j] - U[j] * v[0]) * ir;
+    um += U[j] * v[1 + j];
+  }
+  const T dp = gm1 * (v[4] - um + T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W) * v[0]);
+  const T Ud = U[D];
+  out[0] = v[1 + D];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) out[1 + j] = v[1 + D] * U[j] + Ud * (v[1 + j] - U[j] * v[0]);
+  out[1 + D] += dp;
+  out[4] = (v[4] + dp) * Ud + (Q[4] + s.p) * dU[D];
+}
+
+// rho <A psi> = -sum_e J_e(Q) dQ/dx_e
+template <class T>
+DGK_HD void euler_dt(const Prim<T>& s, const T Q[5], T gm1, const T dq[3][5], T out[5]) {
+  T j0[5], j1[5], j2[5];
+  euler_jvp<0>(s, Q, gm1, dq[0], j0);
+  euler_jvp<1>(s, Q, gm1, dq[1], j1);
+  euler_jvp<2>(s, Q, gm1, dq[2], j2);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) out[k] = -(j0[k] + j1[k] + j2[k]);
+}
+
+// Identity (ii) along axis D, without the factor p.
+template <int D, class T>
+DGK_HD void ns_moment(const Prim<T>& s, const Grad<T>& g, T two_k3, T cp, T out[5]) {
+  const T U[3] = {s.U, s.V, s.W};
+  const T div = g.dU[0][0] + g.dU[1][1] + g.dU[2][2];
+  T ud = T(0);
+  out[0] = T(0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    T Dj = g.dU[D][j] + g.dU[j][D];
+    if (j == D) Dj -= two_k3 * div;
+    out[1 + j] = Dj;
+    ud += U[j] * Dj;
+  }
+  out[4] = ud + cp * g.dT[D];
+}
+
+// --------------------------------------------------------------------------
+// Face flux, Eq. (flux) in the local frame of the face (normal = axis 0).
+// The two sides are processed one after the other (face_side) into the
+// accumulators below, then face_finish forms g0, its slopes and the fluxes.
+//   Q0   = rho_l <psi>_{u>0, l} + rho_r <psi>_{u<0, r}
+//   dQ0_i= rho_l <a_i^l psi>_{u>0} + rho_r <a_i^r psi>_{u<0}
+//   m4 = sum rho_k <u psi>_{k}, m5 = sum rho_k <u (a^k.u) psi>_k,
+//   m6 = sum rho_k <u A^k psi>_k   (half spaces of the two sides)
+//   m1 = rho0 <u psi>_0, m3 = rho0 <u Abar psi>_0, m2 = rho0 <u (abar.u) psi>_0
+// --------------------------------------------------------------------------
+template <class T>
+struct FaceAcc {
+  T Q0[5], dQ0[3][5], m4[5], m5[5], m6[5];
+};
+
+template <class T>
+DGK_HD void face_acc_zero(FaceAcc<T>& a) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    a.Q0[k] = a.m4[k] = a.m5[k] = a.m6[k] = T(0);
+    a.dQ0[0][k] = a.dQ0[1][k] = a.dQ0[2][k] = T(0);
+  }
+}
+
+// SIDE = +1: lower cell (half space u > 0); SIDE = -1: upper cell (u < 0).
+template <int SIDE, class T>
+DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>& acc, int& bad) {
   const T K = T(ph.K), gm1 = T(ph.gm1);
-  const Prim<T> sL = primitive(qL, gm1), sR = primitive(qR, gm1);
-  bad |= int(unphysical(sL)) | int(unphysical(sR));
-  const Mom<T> fL = moments_full(sL, K), fR = moments_full(sR, K);
-  const Mom<T> hL = moments_half(sL, fL, +1), hR = moments_half(sR, fR, -1);
-
-  // microscopic slopes of the two sides and their time slopes (compatibility)
-  T aL[3][5], aR[3][5], AL[5], AR[5];
-  {
-    const Solver5<T> SL(sL, K), SR(sR, K);
-    T bL[5], bR[5];
-    const T irL = T(1) / sL.rho, irR = T(1) / sR.rho;
+  const Prim<T> s = primitive(q, gm1);
+  bad |= int(unphysical(s));
+  const Solver5<T> S(s, K, T(ph.inv_k3));
+  const T ir = s.ir;
+  // slopes: <a_i psi> = dQ/dn_i / rho, time slope from the compatibility condition
+  T a[3][5], A[5], b[5];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 3; ++i) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        bL[k] = dqL[i][k] * irL;
-        bR[k] = dqR[i][k] * irR;
-      }
-      SL(bL, aL[i]);
-      SR(bR, aR[i]);
-    }
-    T y0[5], y1[5], y2[5];
-    Gpsi<1, 0, 0>(fL, aL[0], y0);
-    Gpsi<0, 1, 0>(fL, aL[1], y1);
-    Gpsi<0, 0, 1>(fL, aL[2], y2);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) bL[k] = -(y0[k] + y1[k] + y2[k]);
-    SL(bL, AL);
-    Gpsi<1, 0, 0>(fR, aR[0], y0);
-    Gpsi<0, 1, 0>(fR, aR[1], y1);
-    Gpsi<0, 0, 1>(fR, aR[2], y2);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) bR[k] = -(y0[k] + y1[k] + y2[k]);
-    SR(bR, AR);
+    for (int k = 0; k < 5; ++k) b[k] = dq[i][k] * ir;
+    S(b, a[i]);
   }
-
-  // equilibrium state at the interface and its directional derivatives
-  T Q0[5], dQ0[3][5];
-  {
-    T pL[5], pR[5];
-    psim<0, 0, 0>(hL, pL);
-    psim<0, 0, 0>(hR, pR);
+  euler_dt(s, q, gm1, dq, b);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Q0[k] = sL.rho * pL[k] + sR.rho * pR[k];
+  for (int k = 0; k < 5; ++k) b[k] *= ir;
+  S(b, A);
+  // half-space moments (normal velocity on the side's half line)
+  Mom<T> h;
+  mom_half(s.U, s.th, SIDE, h.u);
+  mom_full(s.V, s.th, h.v);
+  mom_full(s.W, s.th, h.w);
+  mom_xi(K, s.th, h);
+  const T r = s.rho;
+  T y[5], z0[5], z1[5], z2[5];
+  psim<0, 0, 0>(h, y);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      Gpsi<0, 0, 0>(hL, aL[i], pL);
-      Gpsi<0, 0, 0>(hR, aR[i], pR);
+  for (int k = 0; k < 5; ++k) acc.Q0[k] += r * y[k];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) dQ0[i][k] = sL.rho * pL[k] + sR.rho * pR[k];
-    }
+  for (int i = 0; i < 3; ++i) {
+    Gpsi<0, 0, 0>(h, a[i], y);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc.dQ0[i][k] += r * y[k];
   }
-  const Prim<T> s0 = primitive(Q0, gm1);
-  bad |= unphysical(s0);
-  const Mom<T> f0 = moments_full(s0, K);
-  T ab[3][5], Ab[5];
-  {
-    const Solver5<T> S0(s0, K);
-    const T ir0 = T(1) / s0.rho;
-    T b[5];
+  psim<1, 0, 0>(h, y);
+  Gpsi<2, 0, 0>(h, a[0], z0);
+  Gpsi<1, 1, 0>(h, a[1], z1);
+  Gpsi<1, 0, 1>(h, a[2], z2);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b[k] = dQ0[i][k] * ir0;
-      S0(b, ab[i]);
-    }
-    T y0[5], y1[5], y2[5];
-    Gpsi<1, 0, 0>(f0, ab[0], y0);
-    Gpsi<0, 1, 0>(f0, ab[1], y1);
-    Gpsi<0, 0, 1>(f0, ab[2], y2);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = -(y0[k] + y1[k] + y2[k]);
-    S0(b, Ab);
+  for (int k = 0; k < 5; ++k) {
+    acc.m4[k] += r * y[k];
+    acc.m5[k] += r * (z0[k] + z1[k] + z2[k]);
   }
+  Gpsi<1, 0, 0>(h, A, y);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) acc.m6[k] += r * y[k];
+}
 
-  // flux moments of the six parts of Eq. (flux)
-  T m[6][5];
-  {
-    T y0[5], y1[5], y2[5];
-    psim<1, 0, 0>(f0, m[0]);
-    Gpsi<2, 0, 0>(f0, ab[0], y0);
-    Gpsi<1, 1, 0>(f0, ab[1], y1);
-    Gpsi<1, 0, 1>(f0, ab[2], y2);
+template <class T, bool NEED_F>
+DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], int& bad) {
+  const T K = T(ph.K), gm1 = T(ph.gm1);
+  const Prim<T> s0 = primitive(acc.Q0, gm1);
+  bad |= int(unphysical(s0));
+  T m1[5], m2[5], m3[5], dt0[5];
+  euler_flux<0>(s0, acc.Q0, m1);
+  euler_dt(s0, acc.Q0, gm1, acc.dQ0, dt0);  // rho0 <Abar psi>
+  euler_jvp<0>(s0, acc.Q0, gm1, dt0, m3);
+  const Grad<T> g = prim_grad(s0, acc.dQ0, gm1);
+  T ns[5];
+  ns_moment<0>(s0, g, T(2.0 * ph.inv_k3), T(ph.cp), ns);  // (m2 + m3) / p0
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      m[0][k] *= s0.rho;
-      m[1][k] = s0.rho * (y0[k] + y1[k] + y2[k]);
-    }
-    Gpsi<1, 0, 0>(f0, Ab, y0);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[2][k] = s0.rho * y0[k];
+  for (int k = 0; k < 5; ++k) m2[k] = s0.p * ns[k] - m3[k];
 
-    T zL[5], zR[5];
-    psim<1, 0, 0>(hL, zL);
-    psim<1, 0, 0>(hR, zR);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[3][k] = sL.rho * zL[k] + sR.rho * zR[k];
-    Gpsi<2, 0, 0>(hL, aL[0], y0);
-    Gpsi<1, 1, 0>(hL, aL[1], y1);
-    Gpsi<1, 0, 1>(hL, aL[2], y2);
-    Gpsi<2, 0, 0>(hR, aR[0], zL);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[4][k] = sL.rho * (y0[k] + y1[k] + y2[k]) + sR.rho * zL[k];
-    Gpsi<1, 1, 0>(hR, aR[1], y0);
-    Gpsi<1, 0, 1>(hR, aR[2], y1);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[4][k] += sR.rho * (y0[k] + y1[k]);
-    Gpsi<1, 0, 0>(hL, AL, y0);
-    Gpsi<1, 0, 0>(hR, AR, y1);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[5][k] = sL.rho * y0[k] + sR.rho * y1[k];
-  }
-
-  const double tau = ph.mu / double(s0.p);
+  const double ip0 = 1.0 / double(s0.p);
   double al[6], be[6];
-  time_coefficients(tau, ph.dt, al, be);
+  time_coefficients(ph.mu * ip0, ph.half_dt_over_mu * double(s0.p), ph.dt, ph.inv_dt, al, be);
+  const T* mm[6] = {m1, m2, m3, acc.m4, acc.m5, acc.m6};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     double ft = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) ft += be[j] * double(m[j][k]);
+    for (int j = 0; j < 6; ++j) ft += be[j] * double(mm[j][k]);
     Ft[k] = T(ft);
   }
   if constexpr (NEED_F) {
-    double f[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      double s = 0.0;
+      double f = 0.0;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) s += al[j] * double(m[j][k]);
-      f[k] = s;
+      for (int j = 0; j < 6; ++j) f += al[j] * double(mm[j][k]);
+      F[k] = T(f);
     }
-    // Heat flux of the non-equilibrium part -tau g0 (abar.u + Abar):
-    // q = -tau rho0 <(u - U0) (|u - U0|^2 + xi^2)/2 X>.  Writing
-    // (|u-U0|^2 + xi^2)/2 = c.psi with c = (|U0|^2/2, -U0, -V0, -W0, 1) and using
-    // <X psi> = 0 (compatibility), q = -tau c.(m2 + m3).
-    const double U0 = s0.U, V0 = s0.V, W0 = s0.W;
-    const double cc[5] = {0.5 * (U0 * U0 + V0 * V0 + W0 * W0), -U0, -V0, -W0, 1.0};
-    double q = 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) q += cc[k] * (double(m[1][k]) + double(m[2][k]));
-    f[4] += ph.inv_pr_m1 * (-tau * q);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) F[k] = T(f[k]);
+    // Prandtl fix: the heat flux of -tau g0 (abar.u + Abar) is
+    // q = -tau p0 c_p dT0/dn = -mu c_p dT0/dn; add (1/Pr - 1) q.
+    const double q = -ph.mu * ph.cp * double(g.dT[0]);
+    F[4] = T(double(F[4]) + ph.inv_pr_m1 * q);
   }
 }
 
-// --------------------------------------------------------------------------
-// Volume flux (global frame).  q, dq[e] = dQ/dx_e; F[d], Ft[d] for d = x,y,z.
-// F_d = rho [<u_d psi> - tau (sum_e <u_d u_e a_e psi> + <u_d A psi>)] + Pr term,
-// Ft_d = rho <u_d A psi>.
-// --------------------------------------------------------------------------
-template <int D, int E>
-struct UDE {
-  static constexpr int a = (D == 0) + (E == 0), b = (D == 1) + (E == 1), c = (D == 2) + (E == 2);
-};
+template <class T, bool NEED_F>
+DGK_HD void face_flux_local(const Phys& ph, const T qL[5], const T dqL[3][5], const T qR[5], const T dqR[3][5],
+                            T F[5], T Ft[5], int& bad) {
+  FaceAcc<T> acc;
+  face_acc_zero(acc);
+  face_side<+1>(ph, qL, dqL, acc, bad);
+  face_side<-1>(ph, qR, dqR, acc, bad);
+  face_finish<T, NEED_F>(ph, acc, F, Ft, bad);
+}
 
+// --------------------------------------------------------------------------
+// Volume flux, Eq. (flux-2), global frame.  By identities (i), (ii) its
+// moments are F_d = F_d^Euler(Q) - mu (0, D_d, U.D_d + c_p/Pr dT/dx_d) and
+// Ft_d = J_d(Q) rho <A psi> with rho <A psi> = -sum_e J_e(Q) dQ/dx_e.
+// --------------------------------------------------------------------------
 template <class T, bool NEED_F>
 DGK_HD void volume_flux(const Phys& ph, const T q[5], const T dq[3][5], T F[3][5], T Ft[3][5], int& bad) {
   const T K = T(ph.K), gm1 = T(ph.gm1);
   const Prim<T> s = primitive(q, gm1);
-  bad |= unphysical(s);
-  const Mom<T> t = moments_full(s, K);
-  const Solver5<T> S(s, K);
-  T a[3][5], A[5];
-  {
-    const T ir = T(1) / s.rho;
-    T b[5];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) b[k] = dq[e][k] * ir;
-      S(b, a[e]);
-    }
-    T y0[5], y1[5], y2[5];
-    Gpsi<1, 0, 0>(t, a[0], y0);
-    Gpsi<0, 1, 0>(t, a[1], y1);
-    Gpsi<0, 0, 1>(t, a[2], y2);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = -(y0[k] + y1[k] + y2[k]);
-    S(b, A);
-  }
-  T uA[3][5];
-  Gpsi<1, 0, 0>(t, A, uA[0]);
-  Gpsi<0, 1, 0>(t, A, uA[1]);
-  Gpsi<0, 0, 1>(t, A, uA[2]);
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int k = 0; k < 5; ++k) Ft[d][k] = s.rho * uA[d][k];
+  bad |= int(unphysical(s));
+  T dt[5];
+  euler_dt(s, q, gm1, dq, dt);
+  euler_jvp<0>(s, q, gm1, dt, Ft[0]);
+  euler_jvp<1>(s, q, gm1, dt, Ft[1]);
+  euler_jvp<2>(s, q, gm1, dt, Ft[2]);
   if constexpr (NEED_F) {
-    const T tau = T(ph.mu) / s.p;
-    const T cc[5] = {T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W), -s.U, -s.V, -s.W, T(1)};
-    const T prf = T(ph.inv_pr_m1);
+    const Grad<T> g = prim_grad(s, dq, gm1);
+    const T mu = T(ph.mu);
+    const T heat = mu * T(ph.inv_pr_m1) * T(ph.cp);  // extra heat-flux factor of 1/Pr - 1
     static_for<3>([&](auto dc) {
       constexpr int d = decltype(dc)::value;
-      T visc[5], y0[5], y1[5], y2[5], e0[5];
-      Gpsi<UDE<d, 0>::a, UDE<d, 0>::b, UDE<d, 0>::c>(t, a[0], y0);
-      Gpsi<UDE<d, 1>::a, UDE<d, 1>::b, UDE<d, 1>::c>(t, a[1], y1);
-      Gpsi<UDE<d, 2>::a, UDE<d, 2>::b, UDE<d, 2>::c>(t, a[2], y2);
-      psim<d == 0, d == 1, d == 2>(t, e0);
-      T qh = T(0);
+      T e[5], ns[5];
+      euler_flux<d>(s, q, e);
+      ns_moment<d>(s, g, T(2.0 * ph.inv_k3), T(ph.cp), ns);
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        visc[k] = uA[d][k] + y0[k] + y1[k] + y2[k];
-        qh += cc[k] * visc[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 5; ++k) F[d][k] = s.rho * (e0[k] - tau * visc[k]);
-      // heat flux of -tau g (a.u + A), same reduction as on the faces
-      F[d][4] += prf * (-tau * s.rho * qh);
+      for (int k = 0; k < 5; ++k) F[d][k] = e[k] - mu * ns[k];
+      F[d][4] -= heat * g.dT[d];
     });
   }
 }

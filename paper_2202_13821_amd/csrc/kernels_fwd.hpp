@@ -204,9 +204,9 @@ DGK_D void face_block(const T* __restrict__ q, T* __restrict__ rec, const Geo& g
     const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
     // local frame: velocity (normal, t1, t2) = global (D, T1, T2)
     constexpr int vmap[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};
-    T qs[2][5], dqs[2][3][5];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
+    // trace of one side at the point: Q and its derivatives along (n, t1, t2)
+    auto trace = [&](auto side_c, T qs[5], T dqs[3][5]) {
+      constexpr int side = decltype(side_c)::value;
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
         const T* c = &sq[side][fl][vmap[vl] * NM];
@@ -216,25 +216,36 @@ DGK_D void face_block(const T* __restrict__ q, T* __restrict__ rec, const Geo& g
           constexpr Modes<K> md{};
           constexpr int ed = md.e[n][D], e1 = md.e[n][T1], e2 = md.e[n][T2];
           // P_ed(+1) = 1, P_ed(-1) = (-1)^ed; P'_ed(+1) = ed(ed+1)/2, P'_ed(-1) = (-1)^(ed+1) ed(ed+1)/2
-          constexpr double pv0 = 1.0, pv1 = (ed % 2) ? -1.0 : 1.0;
-          constexpr double dv0 = 0.5 * ed * (ed + 1), dv1 = ((ed % 2) ? 1.0 : -1.0) * 0.5 * ed * (ed + 1);
-          const T pv = T(side == 0 ? pv0 : pv1), dv = T(side == 0 ? dv0 : dv1);
+          constexpr double pv = (side == 0) ? 1.0 : ((ed % 2) ? -1.0 : 1.0);
+          constexpr double dv = ((side == 0) ? 1.0 : ((ed % 2) ? 1.0 : -1.0)) * 0.5 * ed * (ed + 1);
           const T cn = c[n];
           const T t12 = Pa[e1] * Pb[e2];
-          v0 += cn * (pv * t12);
-          if constexpr (ed > 0) vn += cn * (dv * t12);
-          if constexpr (e1 > 0) v1 += cn * (pv * dPa[e1] * Pb[e2]);
-          if constexpr (e2 > 0) v2 += cn * (pv * Pa[e1] * dPb[e2]);
+          v0 += cn * (T(pv) * t12);
+          if constexpr (ed > 0) vn += cn * (T(dv) * t12);
+          if constexpr (e1 > 0) v1 += cn * (T(pv) * dPa[e1] * Pb[e2]);
+          if constexpr (e2 > 0) v2 += cn * (T(pv) * Pa[e1] * dPb[e2]);
         });
-        qs[side][vl] = v0;
-        dqs[side][0][vl] = vn * sn;
-        dqs[side][1][vl] = v1 * s1;
-        dqs[side][2][vl] = v2 * s2;
+        qs[vl] = v0;
+        dqs[0][vl] = vn * sn;
+        dqs[1][vl] = v1 * s1;
+        dqs[2][vl] = v2 * s2;
       }
-    }
+    };
     T F[5], Ft[5];
     int bad = 0;
-    face_flux_local<T, NEED_F>(ph, qs[0], dqs[0], qs[1], dqs[1], F, Ft, bad);
+    FaceAcc<T> acc;
+    face_acc_zero(acc);
+    {
+      T qs[5], dqs[3][5];
+      trace(std::integral_constant<int, 0>{}, qs, dqs);
+      face_side<+1>(ph, qs, dqs, acc, bad);
+    }
+    {
+      T qs[5], dqs[3][5];
+      trace(std::integral_constant<int, 1>{}, qs, dqs);
+      face_side<-1>(ph, qs, dqs, acc, bad);
+    }
+    face_finish<T, NEED_F>(ph, acc, F, Ft, bad);
     if (bad) atomicOr(flag, 1);
     // back to global variable order
 #pragma unroll
@@ -264,8 +275,20 @@ DGK_D void face_block(const T* __restrict__ q, T* __restrict__ rec, const Geo& g
   }
 }
 
+// Minimum waves per SIMD requested for the face kernel (register budget).
+#ifndef DGK_FACE_WAVES_F32
+#define DGK_FACE_WAVES_F32 3
+#endif
+#ifndef DGK_FACE_WAVES_F64
+#define DGK_FACE_WAVES_F64 1
+#endif
+template <class T>
+struct FaceWaves {
+  static constexpr int value = sizeof(T) == 4 ? DGK_FACE_WAVES_F32 : DGK_FACE_WAVES_F64;
+};
+
 template <class T, int K, int NQ, bool NEED_F>
-__global__ __launch_bounds__(256) void face_kernel(const T* __restrict__ q, T* __restrict__ rec, Geo g, Phys ph,
+__global__ __launch_bounds__(256, FaceWaves<T>::value) void face_kernel(const T* __restrict__ q, T* __restrict__ rec, Geo g, Phys ph,
                                                    int* flag) {
   using C = FaceCfg<K, NQ>;
   __shared__ T sq[2][C::FPB][C::CS];

@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -72,6 +74,68 @@ def time_path(precision, n, steps, warmup, timing=True):
     s.set_timing(False)
     s.check()
     return (t1 - t0) / steps, kern, q, s
+
+
+def adjoint_ratio(precision, n=32, nsteps=200, stride=15):
+    """adj/fwd on the P2 Taylor-Green 32^3 adjoint configuration: wall time of
+    the gradient call (segment recomputation + reverse sweep) over that of the
+    checkpointing forward call."""
+    import torch
+
+    from paper_2202_13821_amd import Solver, kinetic_energy, problems
+
+    q0, lo, hi = problems.tgv((n, n, n), 2)
+    dt = problems.tgv_dt(n)
+    s = Solver((n, n, n), lo, hi, 2, mu=1.0 / 1600.0, prandtl=0.72, precision=precision, device="cuda:0",
+               max_stride=stride)
+    ck = s.new_checkpoints(nsteps, stride)
+    q = torch.as_tensor(q0, device="cuda:0")
+    # warm-up of both paths
+    s.step(q.clone(), dt, 2, ck, stride)
+    qq = q.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(kinetic_energy(qq, s), qq)
+    s.adjoint(ck, stride, dt, 2, g.contiguous())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qN = q.clone()
+    s.step(qN, dt, nsteps, ck, stride)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    qq = qN.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(kinetic_energy(qq, s), qq)
+    g = g.contiguous()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.adjoint(ck, stride, dt, nsteps, g)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    return {"fwd_s": t1 - t0, "adj_s": t3 - t2, "adj_over_fwd": (t3 - t2) / (t1 - t0),
+            "workload": f"P2 TGV {n}^3, {nsteps} steps, checkpoint stride {stride}"}
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2202_13821_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hpp", ".hip")):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_tgv128.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("kernels", {}).get(kernel_key, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(n, seconds):
@@ -131,10 +195,20 @@ def main():
         npts_face = 3 * n ** 3 * 9
         w = 0.5 * (flops["fp32"]["face_stage1"] + flops["fp32"]["face_stage2"]) * npts_face
         achieved = w / (face_ms * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "face_kernel<float,2,3>", "achieved": achieved,
-                           "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
-                           "frac": achieved / MI355X_PEAK["fp32_vector"], "traffic": None,
+        out["roofline"] = {"bound": "alu", "kernel": "face_kernel<float,2,3> (both stages, averaged per launch)",
+                           "achieved": achieved, "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
+                           "frac": achieved / MI355X_PEAK["fp32_vector"],
+                           "traffic": measured_traffic("face_kernel<float,2,3>"),
+                           "flops_per_launch": w, "avg_launch_ms": face_ms,
                            "flops_per_point": 0.5 * (flops["fp32"]["face_stage1"] + flops["fp32"]["face_stage2"])}
+        wv = 0.5 * (flops["fp32"]["volume_stage1"] + flops["fp32"]["volume_stage2"]) * 27 * n ** 3
+        out["roofline_volume"] = {"bound": "alu", "achieved": wv / (vol_ms * 1e-3) / 1e12,
+                                  "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
+                                  "frac": wv / (vol_ms * 1e-3) / 1e12 / MI355X_PEAK["fp32_vector"],
+                                  "traffic": measured_traffic("volume_kernel<float,2,3>")}
+        per_step = flops["per_step_per_cell"]["fp32"] * n ** 3
+        out["step_flops"] = per_step
+        out["step_tflops"] = per_step / sec32 / 1e12
     if not a.no_fp64:
         del s32
         sec64, k64, q64, s64 = time_path("fp64", n, a.steps, a.warmup)
@@ -147,6 +221,18 @@ def main():
         out["rel_l2_fp32_bulk_vs_fp64"] = max(
             float(torch.linalg.norm(d[list(g)]) / torch.linalg.norm(r[list(g)])) for g in groups)
         del s64
+    if not a.no_adjoint:
+        out["adjoint"] = {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64")}
+        out["adj_over_fwd"] = out["adjoint"]["fp32_bulk"]["adj_over_fwd"]
+    if a.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+        del x, y
+    out["kernel_source_hash"] = kernel_source_hash()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -363,8 +363,10 @@ __global__ __launch_bounds__(64 * NQ) void volume_kernel(const T* __restrict__ q
   constexpr int NR = CPB * 5 * NF;  // rows of the projection: (cell, var, F|Ft)
   constexpr int NRT = (NR + 15) / 16;
   constexpr int RECN = 5 * NF * NT;
+  // sA holds the MFMA operand, then the block's face records
+  constexpr int NRA = (NR * KK >= 6 * CPB * RECN) ? NR : (6 * CPB * RECN + KK - 1) / KK;
   __shared__ T sq[CPB][C::CS];
-  __shared__ T sA[NR][KK];
+  __shared__ T sA[NRA][KK];
   __shared__ T sR[NR][NM];
   const int tid = threadIdx.x;
   const long long N = g.ncell;
@@ -459,6 +461,23 @@ __global__ __launch_bounds__(64 * NQ) void volume_kernel(const T* __restrict__ q
   }
   __syncthreads();
 
+  // face records of the block's cells, staged through LDS with coalesced
+  // loads (the MFMA operand space is free now): sRec[d][0][j] = upper face of
+  // cell j, sRec[d][1][j] = its lower face (upper face of the cell below).
+  static_assert(6 * CPB * RECN <= NRA * KK, "face records must fit in sA");
+  T(*sRec)[2][CPB][RECN] = reinterpret_cast<T(*)[2][CPB][RECN]>(&sA[0][0]);
+  for (int idx = tid; idx < 6 * CPB * RECN; idx += NTH) {
+    const int r = idx % RECN, t = idx / RECN;
+    const int j = t % CPB, ds = t / CPB;  // ds = d * 2 + side
+    const int d = ds >> 1, side = ds & 1;
+    const long long c = c0 + j;
+    if (c < N) {
+      const long long cf = side ? neighbor_dn(c, d, g) : c;
+      sRec[d][side][j][r] = rec[((long long)d * N + cf) * RECN + r];
+    }
+  }
+  __syncthreads();
+
   // surface terms, M^{-1} and the stage update; item = (var, mode, cell), cell fastest
   const auto& mt = ModeTabHolder<K>::t;
   for (int it = tid; it < CPB * 5 * NM; it += NTH) {
@@ -470,19 +489,17 @@ __global__ __launch_bounds__(64 * NQ) void volume_kernel(const T* __restrict__ q
     double L = NEED_F ? double(sR[(j * 5 + v) * NF][n]) : 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const long long cm = neighbor_dn(c, d, g);
       const int m = mt.tm[n][d];
       const double sg = (mt.nd[n][d] & 1) ? -1.0 : 1.0;
-      const T* ru = &rec[((long long)d * N + c) * RECN];
-      const T* rl = &rec[((long long)d * N + cm) * RECN];
-      const int ot = ((v * NF) + NF - 1) * NT + m;  // Ft part (NF=2: comp = 5 + v)
+      const T* ru = sRec[d][0][j];
+      const T* rl = sRec[d][1][j];
       if constexpr (NEED_F) {
         const int of = v * NT + m;
         const int oft = (5 + v) * NT + m;
         L += g.inv_dx[d] * (sg * double(rl[of]) - double(ru[of]));
         Lt += g.inv_dx[d] * (sg * double(rl[oft]) - double(ru[oft]));
-        (void)ot;
       } else {
+        const int ot = v * NT + m;
         Lt += g.inv_dx[d] * (sg * double(rl[ot]) - double(ru[ot]));
       }
     }

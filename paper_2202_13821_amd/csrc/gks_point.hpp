@@ -383,6 +383,109 @@ DGK_HD void face_acc_zero(FaceAcc<T>& a) {
   }
 }
 
+// Moment matrices of one side.  With the normal velocity u on the side's half
+// line (moments M_n = <u^n>, n = 0..6) and the tangential velocities v, w and
+// xi^2 Gaussian (independent of u), every entry of
+//   H^p_kj = <u^p psi_k psi_j>,  Gv_kj = <u v psi_k psi_j>,  Gw_kj = <u w psi_k psi_j>
+// is a closed form in M_n and the transverse moments below (psi_4 = (u^2 + r)/2
+// with r = v^2 + w^2 + xi^2).  Matrices are symmetric, stored as the upper
+// triangle in row order (00 01 02 03 04 11 12 13 14 22 23 24 33 34 44).
+template <class T>
+struct Transverse {
+  T V, W, v2, w2, v3, w3, R1, R2, vr, wr, v2r, w2r, vwr, vr2, wr2;
+  DGK_HD Transverse(T V_, T W_, T th, T K) : V(V_), W(W_) {
+    const T t2 = th * th;
+    v2 = V * V + th;
+    w2 = W * W + th;
+    v3 = V * (V * V + T(3) * th);
+    w3 = W * (W * W + T(3) * th);
+    const T v4 = V * V * (V * V + T(6) * th) + T(3) * t2;
+    const T w4 = W * W * (W * W + T(6) * th) + T(3) * t2;
+    const T v5 = V * (V * V * (V * V + T(10) * th) + T(15) * t2);
+    const T w5 = W * (W * W * (W * W + T(10) * th) + T(15) * t2);
+    const T s1 = K * th, s2 = K * (K + T(2)) * t2;
+    R1 = v2 + w2 + s1;                                           // <r>
+    R2 = v4 + w4 + s2 + T(2) * (v2 * w2 + (v2 + w2) * s1);      // <r^2>
+    vr = v3 + V * (w2 + s1);                                     // <v r>
+    wr = w3 + W * (v2 + s1);                                     // <w r>
+    v2r = v4 + v2 * (w2 + s1);                                   // <v^2 r>
+    w2r = w4 + w2 * (v2 + s1);                                   // <w^2 r>
+    vwr = v3 * W + V * w3 + V * W * s1;                          // <v w r>
+    vr2 = v5 + T(2) * v3 * (w2 + s1) + V * (w4 + s2 + T(2) * w2 * s1);  // <v r^2>
+    wr2 = w5 + T(2) * w3 * (v2 + s1) + W * (v4 + s2 + T(2) * v2 * s1);  // <w r^2>
+  }
+};
+
+template <int P, class T>
+DGK_HD void mat_H(const T* M, const Transverse<T>& t, T H[15]) {
+  const T h = T(0.5);
+  H[0] = M[P];
+  H[1] = M[P + 1];
+  H[2] = t.V * M[P];
+  H[3] = t.W * M[P];
+  H[4] = h * (M[P + 2] + t.R1 * M[P]);
+  H[5] = M[P + 2];
+  H[6] = t.V * M[P + 1];
+  H[7] = t.W * M[P + 1];
+  H[8] = h * (M[P + 3] + t.R1 * M[P + 1]);
+  H[9] = t.v2 * M[P];
+  H[10] = t.V * t.W * M[P];
+  H[11] = h * (t.V * M[P + 2] + t.vr * M[P]);
+  H[12] = t.w2 * M[P];
+  H[13] = h * (t.W * M[P + 2] + t.wr * M[P]);
+  H[14] = T(0.25) * (M[P + 4] + T(2) * t.R1 * M[P + 2] + t.R2 * M[P]);
+}
+
+template <class T>
+DGK_HD void mat_Gv(const T* M, const Transverse<T>& t, T G[15]) {
+  const T h = T(0.5), VW = t.V * t.W;
+  G[0] = t.V * M[1];
+  G[1] = t.V * M[2];
+  G[2] = t.v2 * M[1];
+  G[3] = VW * M[1];
+  G[4] = h * (t.V * M[3] + t.vr * M[1]);
+  G[5] = t.V * M[3];
+  G[6] = t.v2 * M[2];
+  G[7] = VW * M[2];
+  G[8] = h * (t.V * M[4] + t.vr * M[2]);
+  G[9] = t.v3 * M[1];
+  G[10] = t.v2 * t.W * M[1];
+  G[11] = h * (t.v2 * M[3] + t.v2r * M[1]);
+  G[12] = t.V * t.w2 * M[1];
+  G[13] = h * (VW * M[3] + t.vwr * M[1]);
+  G[14] = T(0.25) * (t.V * M[5] + T(2) * t.vr * M[3] + t.vr2 * M[1]);
+}
+
+template <class T>
+DGK_HD void mat_Gw(const T* M, const Transverse<T>& t, T G[15]) {
+  const T h = T(0.5), VW = t.V * t.W;
+  G[0] = t.W * M[1];
+  G[1] = t.W * M[2];
+  G[2] = VW * M[1];
+  G[3] = t.w2 * M[1];
+  G[4] = h * (t.W * M[3] + t.wr * M[1]);
+  G[5] = t.W * M[3];
+  G[6] = VW * M[2];
+  G[7] = t.w2 * M[2];
+  G[8] = h * (t.W * M[4] + t.wr * M[2]);
+  G[9] = t.W * t.v2 * M[1];
+  G[10] = t.V * t.w2 * M[1];
+  G[11] = h * (VW * M[3] + t.vwr * M[1]);
+  G[12] = t.w3 * M[1];
+  G[13] = h * (t.w2 * M[3] + t.w2r * M[1]);
+  G[14] = T(0.25) * (t.W * M[5] + T(2) * t.wr * M[3] + t.wr2 * M[1]);
+}
+
+// y += r * S x for a symmetric S stored as above
+template <class T>
+DGK_HD void sym_mv_acc(const T S[15], const T x[5], T r, T y[5]) {
+  y[0] += r * (S[0] * x[0] + S[1] * x[1] + S[2] * x[2] + S[3] * x[3] + S[4] * x[4]);
+  y[1] += r * (S[1] * x[0] + S[5] * x[1] + S[6] * x[2] + S[7] * x[3] + S[8] * x[4]);
+  y[2] += r * (S[2] * x[0] + S[6] * x[1] + S[9] * x[2] + S[10] * x[3] + S[11] * x[4]);
+  y[3] += r * (S[3] * x[0] + S[7] * x[1] + S[10] * x[2] + S[12] * x[3] + S[13] * x[4]);
+  y[4] += r * (S[4] * x[0] + S[8] * x[1] + S[11] * x[2] + S[13] * x[3] + S[14] * x[4]);
+}
+
 // SIDE = +1: lower cell (half space u > 0); SIDE = -1: upper cell (u < 0).
 template <int SIDE, class T>
 DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>& acc, int& bad) {
@@ -403,35 +506,33 @@ DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>
 #pragma unroll
   for (int k = 0; k < 5; ++k) b[k] *= ir;
   S(b, A);
-  // half-space moments (normal velocity on the side's half line)
-  Mom<T> h;
-  mom_half(s.U, s.th, SIDE, h.u);
-  mom_full(s.V, s.th, h.v);
-  mom_full(s.W, s.th, h.w);
-  mom_xi(K, s.th, h);
+  // half-space moments of the normal velocity, transverse Gaussian moments
+  T M[7];
+  mom_half(s.U, s.th, SIDE, M);
+  const Transverse<T> tr(s.V, s.W, s.th, K);
   const T r = s.rho;
-  T y[5], z0[5], z1[5], z2[5];
-  psim<0, 0, 0>(h, y);
+  T H[15];
+  mat_H<0>(M, tr, H);  // <psi psi^T>
+  acc.Q0[0] += r * H[0];
+  acc.Q0[1] += r * H[1];
+  acc.Q0[2] += r * H[2];
+  acc.Q0[3] += r * H[3];
+  acc.Q0[4] += r * H[4];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) acc.Q0[k] += r * y[k];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    Gpsi<0, 0, 0>(h, a[i], y);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) acc.dQ0[i][k] += r * y[k];
-  }
-  psim<1, 0, 0>(h, y);
-  Gpsi<2, 0, 0>(h, a[0], z0);
-  Gpsi<1, 1, 0>(h, a[1], z1);
-  Gpsi<1, 0, 1>(h, a[2], z2);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    acc.m4[k] += r * y[k];
-    acc.m5[k] += r * (z0[k] + z1[k] + z2[k]);
-  }
-  Gpsi<1, 0, 0>(h, A, y);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) acc.m6[k] += r * y[k];
+  for (int i = 0; i < 3; ++i) sym_mv_acc(H, a[i], r, acc.dQ0[i]);
+  mat_H<1>(M, tr, H);  // <u psi psi^T>
+  acc.m4[0] += r * H[0];
+  acc.m4[1] += r * H[1];
+  acc.m4[2] += r * H[2];
+  acc.m4[3] += r * H[3];
+  acc.m4[4] += r * H[4];
+  sym_mv_acc(H, A, r, acc.m6);
+  mat_H<2>(M, tr, H);  // <u^2 psi psi^T>
+  sym_mv_acc(H, a[0], r, acc.m5);
+  mat_Gv(M, tr, H);  // <u v psi psi^T>
+  sym_mv_acc(H, a[1], r, acc.m5);
+  mat_Gw(M, tr, H);  // <u w psi psi^T>
+  sym_mv_acc(H, a[2], r, acc.m5);
 }
 
 template <class T, bool NEED_F>

@@ -149,14 +149,17 @@ DGK_D void adj_face_block(const T* __restrict__ q, const AdjIn<STAGE>& in, doubl
   const long long N = g.ncell;
   const auto& mt = ModeTabHolder<K>::t;
 
-  // coefficients of the lower (side 0) and upper (side 1) cells
+  // upper neighbours, then the coefficients of the lower (side 0) and upper (side 1) cells
+  __shared__ unsigned snb[FPB];
+  if (tid < FPB && f0 + tid < N) snb[tid] = nb32(unsigned(f0 + tid), D, +1, g);
+  __syncthreads();
   for (int idx = tid; idx < 2 * FPB * 5 * NM; idx += 256) {
     const int side = idx / (FPB * 5 * NM);
     const int r = idx - side * (FPB * 5 * NM);
     const int vm = r / FPB, j = r - vm * FPB;
     const long long f = f0 + j;
     if (f < N) {
-      const long long c = side ? neighbor_up<D>(f, g) : f;
+      const long long c = side ? (long long)snb[j] : f;
       sq[side][j][vm] = q[(long long)vm * N + c];
     }
   }
@@ -170,7 +173,7 @@ DGK_D void adj_face_block(const T* __restrict__ q, const AdjIn<STAGE>& in, doubl
     const long long f = f0 + j;
     double acc = 0.0;
     if (f < N && (!isF || NEED_F)) {
-      const long long cr = neighbor_up<D>(f, g);
+      const long long cr = (long long)snb[j];
 #pragma unroll
       for (int n = 0; n < NM; ++n) {
         if (mt.tm[n][D] != m) continue;
@@ -415,6 +418,12 @@ __global__ __launch_bounds__(64 * NQ) void adj_volume_kernel(const T* __restrict
   }
   __syncthreads();
   // transposed evaluation, surface records, step-level combination
+  __shared__ unsigned sdn[3][CPB];
+  if (tid < 3 * CPB) {
+    const int d = tid / CPB, j = tid % CPB;
+    if (c0 + j < N) sdn[d][j] = nb32(unsigned(c0 + j), d, -1, g);
+  }
+  __syncthreads();
   const auto& vb = VolBasisHolder<T, K, NQ>::t;
   for (int it = tid; it < CPB * 5 * NM; it += NTH) {
     const int j = it % CPB, vm = it / CPB;
@@ -429,7 +438,7 @@ __global__ __launch_bounds__(64 * NQ) void adj_volume_kernel(const T* __restrict
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const long long cm = neighbor_dn(c, d, g);
+      const long long cm = (long long)sdn[d][j];
       s += frec[(((long long)d * N + c) * 2 + 0) * 5 * NM + vm];
       s += frec[(((long long)d * N + cm) * 2 + 1) * 5 * NM + vm];
     }

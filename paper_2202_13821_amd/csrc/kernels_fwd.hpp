@@ -32,32 +32,15 @@ struct Geo {
   double inv_dx[3];      // |Gamma_d| / |K| = 1 / dx_d
 };
 
-template <int D>
-DGK_D long long neighbor_up(long long c, const Geo& g) {
-  if constexpr (D == 0) {
-    int i = int(c % g.nx);
-    return (i + 1 == g.nx) ? c - (g.nx - 1) : c + 1;
-  } else if constexpr (D == 1) {
-    int j = int((c / g.nx) % g.ny);
-    return (j + 1 == g.ny) ? c - (long long)(g.ny - 1) * g.nx : c + g.nx;
-  } else {
-    const long long pl = (long long)g.nx * g.ny;
-    int k = int(c / pl);
-    return (k + 1 == g.nz) ? c - (long long)(g.nz - 1) * pl : c + pl;
-  }
-}
-DGK_D long long neighbor_dn(long long c, int d, const Geo& g) {
-  if (d == 0) {
-    int i = int(c % g.nx);
-    return (i == 0) ? c + (g.nx - 1) : c - 1;
-  } else if (d == 1) {
-    int j = int((c / g.nx) % g.ny);
-    return (j == 0) ? c + (long long)(g.ny - 1) * g.nx : c - g.nx;
-  } else {
-    const long long pl = (long long)g.nx * g.ny;
-    int k = int(c / pl);
-    return (k == 0) ? c + (long long)(g.nz - 1) * pl : c - pl;
-  }
+// Neighbour of cell c across its upper (+1) or lower (-1) face along axis d,
+// periodic, in 32-bit arithmetic (the cell count is below 2^31).
+DGK_D unsigned nb32(unsigned c, int d, int off, const Geo& g) {
+  const unsigned nx = unsigned(g.nx), ny = unsigned(g.ny), nz = unsigned(g.nz);
+  const unsigned i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+  if (d == 0) return (off > 0) ? (i + 1 == nx ? c - i : c + 1) : (i == 0 ? c + nx - 1 : c - 1);
+  if (d == 1) return (off > 0) ? (j + 1 == ny ? c - j * nx : c + nx) : (j == 0 ? c + (ny - 1) * nx : c - nx);
+  const unsigned pl = nx * ny;
+  return (off > 0) ? (k + 1 == nz ? c - k * pl : c + pl) : (k == 0 ? c + (nz - 1) * pl : c - pl);
 }
 
 // Runtime-indexed node value of the NQ-point rule.
@@ -174,14 +157,18 @@ DGK_D void face_block(const T* __restrict__ q, T* __restrict__ rec, const Geo& g
   const int tid = threadIdx.x;
   const long long N = g.ncell;
 
-  // stage the coefficients of the lower (side 0) and upper (side 1) cells
+  // upper neighbours of the block's faces, then the coefficients of the lower
+  // (side 0) and upper (side 1) cells
+  __shared__ unsigned snb[FPB];
+  if (tid < FPB && f0 + tid < N) snb[tid] = nb32(unsigned(f0 + tid), D, +1, g);
+  __syncthreads();
   for (int idx = tid; idx < 2 * FPB * 5 * NM; idx += 256) {
     const int side = idx / (FPB * 5 * NM);
     const int r = idx - side * (FPB * 5 * NM);
     const int vm = r / FPB, j = r - vm * FPB;
     const long long f = f0 + j;
     if (f < N) {
-      const long long c = side ? neighbor_up<D>(f, g) : f;
+      const long long c = side ? (long long)snb[j] : f;
       sq[side][j][vm] = q[(long long)vm * N + c];
     }
   }
@@ -466,13 +453,19 @@ __global__ __launch_bounds__(64 * NQ) void volume_kernel(const T* __restrict__ q
   // cell j, sRec[d][1][j] = its lower face (upper face of the cell below).
   static_assert(6 * CPB * RECN <= NRA * KK, "face records must fit in sA");
   T(*sRec)[2][CPB][RECN] = reinterpret_cast<T(*)[2][CPB][RECN]>(&sA[0][0]);
+  __shared__ unsigned sdn[3][CPB];
+  if (tid < 3 * CPB) {
+    const int d = tid / CPB, j = tid % CPB;
+    if (c0 + j < N) sdn[d][j] = nb32(unsigned(c0 + j), d, -1, g);
+  }
+  __syncthreads();
   for (int idx = tid; idx < 6 * CPB * RECN; idx += NTH) {
     const int r = idx % RECN, t = idx / RECN;
     const int j = t % CPB, ds = t / CPB;  // ds = d * 2 + side
     const int d = ds >> 1, side = ds & 1;
     const long long c = c0 + j;
     if (c < N) {
-      const long long cf = side ? neighbor_dn(c, d, g) : c;
+      const long long cf = side ? (long long)sdn[d][j] : c;
       sRec[d][side][j][r] = rec[((long long)d * N + cf) * RECN + r];
     }
   }

@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="profiling aid: run only the adjoint/forward timing (32^3) and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -172,6 +174,10 @@ def main():
         sys.exit(2)
     import torch
 
+    if a.adjoint_only:
+        print(json.dumps({"adjoint": {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64")}}),
+              flush=True)
+        return
     n = a.n
     dof = 5 * 10 * n ** 3
     out = {"metric": "P2 TGV 128^3 DOF-updates/s, FP32-bulk vs FP64 at stated L2 error; adj/fwd",

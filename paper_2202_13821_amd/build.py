@@ -1,30 +1,62 @@
-"""Build the HIP library libdg_hgks.so for gfx950 (in-tree, under lib/)."""
+"""Build the HIP library libdg_hgks.so for gfx950 (in-tree, under lib/).
+
+The C-ABI (csrc/dg_hgks.hip) and one object per compiled configuration
+(csrc/instantiate.hip with -DDGK_T/-DDGK_K/-DDGK_NQ) are compiled in
+parallel, then linked.
+"""
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "dg_hgks.hip")
+CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libdg_hgks.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions (v_pk_*_f32) in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
+# (precision, degree, Gauss points per axis) compiled into the library
+CONFIGS = [(t, k, nq) for t in ("float", "double") for (k, nq) in ((1, 2), (2, 3), (2, 2))]
 
-def build(verbose: bool = False, extra=()) -> str:
+
+def _units():
+    yield "dg_hgks", os.path.join(CSRC, "dg_hgks.hip"), []
+    for t, k, nq in CONFIGS:
+        yield f"inst_{t}_{k}{nq}", os.path.join(CSRC, "instantiate.hip"), [f"-DDGK_T={t}", f"-DDGK_K={k}",
+                                                                         f"-DDGK_NQ={nq}"]
+
+
+def build(verbose: bool = False, extra=(), jobs: int = None) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
-    cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           "-o", LIB + ".tmp", SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    jobs = jobs or max(1, min(len(CONFIGS) + 1, os.cpu_count() or 1, 16))
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="dg_hgks_build_") as tmp:
+        objs, pending = [], []
+        for name, src, defs in _units():
+            obj = os.path.join(tmp, name + ".o")
+            cmd = [HIPCC, *FLAGS, *extra, *defs, *inc, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            while len([p for p in pending if p[0].poll() is None]) >= jobs:
+                pending[0][0].wait()
+                pending.sort(key=lambda p: p[0].poll() is None)
+            pending.append((subprocess.Popen(cmd), cmd))
+            objs.append(obj)
+        failed = [cmd for proc, cmd in pending if proc.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -1,12 +1,8 @@
 // dg_hgks.hip -- host side of the C-ABI in include/dg_hgks.h: parameter
-// validation, workspace carving, the launch sequence of the S2O4 step and of
-// its adjoint, per-kernel event timing and error reporting.
-//
-// Launch sequence of one step (Eq. (two-stage)), all on the caller's stream:
-//   stage 1: face_kernel<F and Ft>   volume_kernel<MODE 0>  -> Q*, P
-//   stage 2: face_kernel<Ft only>    volume_kernel<MODE 1>  -> Q^{n+1}
-// In FP32-bulk mode the kernels read a float copy of the coefficients (written
-// by the stage-2 update for the next step) while Q^n, P and Q^{n+1} stay FP64.
+// validation, workspace carving, dispatch to the compiled configurations,
+// per-kernel event timing, error reporting and the point-flux diagnostics.
+// The launch sequences of the step and of its adjoint are in launch.hpp,
+// compiled once per configuration (instantiate.hip).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,8 +12,9 @@
 #include <vector>
 
 #include "dg_hgks.h"
-#include "kernels_fwd.hpp"
 #include "kernels_adj.hpp"
+#include "kernels_fwd.hpp"
+#include "runtime.hpp"
 
 using namespace dgk;
 
@@ -28,39 +25,9 @@ thread_local std::string g_init_error;
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-struct Layout {
-  size_t flag = 0, qs = 0, qstar = 0, P = 0, rec = 0;
-  size_t adj_states = 0, adj_stars = 0, adj_qbar = 0, adj_qsbar = 0, adj_Lbar = 0, adj_Ltbar = 0, adj_frec = 0,
-         adj_mu = 0, adj_tmp = 0;
-  size_t total = 0;
-};
-
-struct TimingRec {
-  int cls;
-  hipEvent_t a, b;
-};
-
 }  // namespace
 
-struct dg_hgks_ctx {
-  dg_hgks_params p{};
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  int max_stride = 0;
-  Layout lay;
-  long long ncell = 0;
-  int nm = 0, nt = 0;
-  double mu = 0.0;
-  bool flag_ready = false;
-  std::string err;
-  bool timing = false;
-  std::vector<TimingRec> trecs;
-  double t_ms[5] = {0, 0, 0, 0, 0};
-  long long t_n[5] = {0, 0, 0, 0, 0};
-};
-
-namespace {
+namespace dgrt {
 
 int fail(dg_hgks_ctx* c, int code, const std::string& msg) {
   if (c)
@@ -70,11 +37,12 @@ int fail(dg_hgks_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
-#define DG_HIP(ctx, call)                                                                   \
-  do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess) return fail(ctx, DG_HGKS_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace dgrt
+
+namespace {
+
+using dgrt::fail;
+using dgrt::Layout;
 
 bool supported(int k, int nq) { return (k == 1 && nq == 2) || (k == 2 && nq == 3) || (k == 2 && nq == 2); }
 
@@ -114,7 +82,7 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
   L.qs = (Ts == 4) ? take(state * Ts) : 0;
   L.qstar = take(state * Ts);
   L.P = take(state * 8);
-  L.rec = take(3 * N * 10 * nt * Ts);
+  L.rec = take(3 * ((N + 63) / 64 * 64) * 10 * nt * Ts);  // records padded to whole 64-cell tiles
   if (max_stride > 0) {
     L.adj_states = take((size_t)max_stride * state * 8);  // Q^n of each step of a segment
     L.adj_stars = take((size_t)max_stride * state * Ts);  // Q* of each step
@@ -128,35 +96,6 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
   }
   L.total = off;
   return L;
-}
-
-Geo make_geo(const dg_hgks_params& p) {
-  Geo g{};
-  g.nx = p.nx;
-  g.ny = p.ny;
-  g.nz = p.nz;
-  g.ncell = (long long)p.nx * p.ny * p.nz;
-  const int n[3] = {p.nx, p.ny, p.nz};
-  for (int e = 0; e < 3; ++e) {
-    const double dx = (p.hi[e] - p.lo[e]) / n[e];
-    g.two_inv_dx[e] = 2.0 / dx;
-    g.inv_dx[e] = 1.0 / dx;
-  }
-  return g;
-}
-
-Phys make_phys(const dg_hgks_ctx* c, double dt) {
-  Phys ph{};
-  ph.K = (5.0 - 3.0 * c->p.gamma) / (c->p.gamma - 1.0);
-  ph.gm1 = c->p.gamma - 1.0;
-  ph.mu = c->mu;
-  ph.inv_pr_m1 = 1.0 / c->p.prandtl - 1.0;
-  ph.dt = dt;
-  ph.inv_k3 = 1.0 / (ph.K + 3.0);
-  ph.cp = 0.5 * (ph.K + 5.0);
-  ph.half_dt_over_mu = c->mu > 0.0 ? 0.5 * dt / c->mu : 0.0;
-  ph.inv_dt = 1.0 / dt;
-  return ph;
 }
 
 template <class T_, int K_, int NQ_>
@@ -175,6 +114,44 @@ int dispatch(const dg_hgks_params& p, F&& f) {
   return DG_HGKS_EUNSUPPORTED;
 }
 
+}  // namespace
+
+__global__ void clear_flag_kernel(int* f) {
+  if (threadIdx.x == 0) f[0] = 0;
+}
+
+
+namespace dgrt {
+
+dgk::Geo make_geo(const dg_hgks_params& p) {
+  dgk::Geo g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.ncell = (long long)p.nx * p.ny * p.nz;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int e = 0; e < 3; ++e) {
+    const double dx = (p.hi[e] - p.lo[e]) / n[e];
+    g.two_inv_dx[e] = 2.0 / dx;
+    g.inv_dx[e] = 1.0 / dx;
+  }
+  return g;
+}
+
+dgk::Phys make_phys(const dg_hgks_ctx* c, double dt) {
+  dgk::Phys ph{};
+  ph.K = (5.0 - 3.0 * c->p.gamma) / (c->p.gamma - 1.0);
+  ph.gm1 = c->p.gamma - 1.0;
+  ph.mu = c->mu;
+  ph.inv_pr_m1 = 1.0 / c->p.prandtl - 1.0;
+  ph.dt = dt;
+  ph.inv_k3 = 1.0 / (ph.K + 3.0);
+  ph.cp = 0.5 * (ph.K + 5.0);
+  ph.half_dt_over_mu = c->mu > 0.0 ? 0.5 * dt / c->mu : 0.0;
+  ph.inv_dt = 1.0 / dt;
+  return ph;
+}
+
 // ---- event timing -----------------------------------------------------------
 int t_begin(dg_hgks_ctx* c, int cls) {
   if (!c->timing) return DG_HGKS_OK;
@@ -190,6 +167,24 @@ int t_end(dg_hgks_ctx* c) {
   DG_HIP(c, hipEventRecord(c->trecs.back().b, c->stream));
   return DG_HGKS_OK;
 }
+int ensure_flag(dg_hgks_ctx* c) {
+  if (c->flag_ready) return DG_HGKS_OK;
+  clear_flag_kernel<<<1, 64, 0, c->stream>>>((int*)(c->ws + c->lay.flag));
+  DG_HIP(c, hipGetLastError());
+  c->flag_ready = true;
+  return DG_HGKS_OK;
+}
+
+}  // namespace dgrt
+
+namespace {
+
+using dgrt::ensure_flag;
+using dgrt::make_geo;
+using dgrt::make_phys;
+using dgrt::t_begin;
+using dgrt::t_end;
+
 int t_collect(dg_hgks_ctx* c) {
   if (c->trecs.empty()) return DG_HGKS_OK;
   DG_HIP(c, hipStreamSynchronize(c->stream));
@@ -203,222 +198,6 @@ int t_collect(dg_hgks_ctx* c) {
   }
   c->trecs.clear();
   return DG_HGKS_OK;
-}
-
-#define DG_LAUNCH(ctx, cls, ...)                  \
-  do {                                            \
-    int rc_ = t_begin(ctx, cls);                  \
-    if (rc_) return rc_;                          \
-    __VA_ARGS__;                                  \
-    DG_HIP(ctx, hipGetLastError());               \
-    rc_ = t_end(ctx);                             \
-    if (rc_) return rc_;                          \
-  } while (0)
-
-__global__ void clear_flag_kernel(int* f) {
-  if (threadIdx.x == 0) f[0] = 0;
-}
-
-int ensure_flag(dg_hgks_ctx* c) {
-  if (c->flag_ready) return DG_HGKS_OK;
-  clear_flag_kernel<<<1, 64, 0, c->stream>>>((int*)(c->ws + c->lay.flag));
-  DG_HIP(c, hipGetLastError());
-  c->flag_ready = true;
-  return DG_HGKS_OK;
-}
-
-template <class T>
-int launch_convert(dg_hgks_ctx* c, const double* a, T* b, long long n) {
-  const long long nb = std::min<long long>((n + 255) / 256, 65536);
-  DG_LAUNCH(c, 2, (convert_kernel<T><<<dim3((unsigned)nb), 256, 0, c->stream>>>(a, b, n)));
-  return DG_HGKS_OK;
-}
-
-// One operator evaluation (face pass + volume pass).
-template <class T, int K, int NQ, int MODE>
-int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g, const Phys& ph) {
-  using FC = FaceCfg<K, NQ>;
-  using VC = VolCfg<K, NQ>;
-  T* rec = (T*)(c->ws + c->lay.rec);
-  int* flag = (int*)(c->ws + c->lay.flag);
-  const long long N = g.ncell;
-  const unsigned bpd = (unsigned)((N + FC::FPB - 1) / FC::FPB);
-  const unsigned nvb = (unsigned)((N + VC::CPB - 1) / VC::CPB);
-  if constexpr (MODE == 1) {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, rec, g, ph, flag)));
-  } else {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, rec, g, ph, flag)));
-  }
-  DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE><<<dim3(nvb), VC::NTH, 0, c->stream>>>(qin, rec, g, ph, o, flag)));
-  return DG_HGKS_OK;
-}
-
-template <class T, int K, int NQ>
-int run_step(dg_hgks_ctx* c, double* q, double dt, int nsteps, double* ckpt, int stride) {
-  const Geo g = make_geo(c->p);
-  const Phys ph = make_phys(c, dt);
-  const long long n = 5LL * c->nm * g.ncell;
-  constexpr bool bulk = sizeof(T) == 4;
-  T* qs = bulk ? (T*)(c->ws + c->lay.qs) : nullptr;
-  T* qstar = (T*)(c->ws + c->lay.qstar);
-  double* P = (double*)(c->ws + c->lay.P);
-  int rc = ensure_flag(c);
-  if (rc) return rc;
-  if (bulk && nsteps > 0) {
-    rc = launch_convert<T>(c, q, qs, n);
-    if (rc) return rc;
-  }
-  for (int s = 0; s < nsteps; ++s) {
-    if (ckpt && s % stride == 0)
-      DG_HIP(c, hipMemcpyAsync(ckpt + (size_t)(s / stride) * n, q, n * sizeof(double), hipMemcpyDeviceToDevice,
-                               c->stream));
-    const T* qin = bulk ? qs : (const T*)q;
-    VolOut<T> o1{};
-    o1.qn = q;
-    o1.P = P;
-    o1.qstar = qstar;
-    o1.dt = dt;
-    rc = launch_stage<T, K, NQ, 0>(c, qin, o1, g, ph);
-    if (rc) return rc;
-    VolOut<T> o2{};
-    o2.P = P;
-    o2.qnew = q;
-    o2.qshadow = qs;
-    o2.dt = dt;
-    rc = launch_stage<T, K, NQ, 1>(c, qstar, o2, g, ph);
-    if (rc) return rc;
-  }
-  return DG_HGKS_OK;
-}
-
-template <class T, int K, int NQ>
-int run_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* Lt) {
-  const Geo g = make_geo(c->p);
-  const Phys ph = make_phys(c, dt);
-  const long long n = 5LL * c->nm * g.ncell;
-  int rc = ensure_flag(c);
-  if (rc) return rc;
-  const T* qin;
-  if constexpr (sizeof(T) == 4) {
-    T* qs = (T*)(c->ws + c->lay.qs);
-    rc = launch_convert<T>(c, q, qs, n);
-    if (rc) return rc;
-    qin = qs;
-  } else {
-    qin = q;
-  }
-  VolOut<T> o{};
-  o.L = L;
-  o.Lt = Lt;
-  o.dt = dt;
-  return launch_stage<T, K, NQ, 2>(c, qin, o, g, ph);
-}
-
-// Adjoint of one stage: face pass then volume pass (kernels_adj.hpp).
-template <class T, int K, int NQ, int STAGE>
-int launch_adj_stage(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, double* out, const Geo& g,
-                     const Phys& ph) {
-  using FC = FaceCfg<K, NQ>;
-  using VC = VolCfg<K, NQ>;
-  const long long N = g.ncell;
-  const unsigned bpd = (unsigned)((N + FC::FPB - 1) / FC::FPB);
-  const unsigned nvb = (unsigned)((N + VC::CPB - 1) / VC::CPB);
-  double* frec = (double*)(c->ws + c->lay.adj_frec);
-  double* mu = (double*)(c->ws + c->lay.adj_mu);
-  DG_LAUNCH(c, 3, (adj_face_kernel<T, K, NQ, STAGE><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, in, frec, g, ph, mu)));
-  DG_LAUNCH(c, 4, (adj_volume_kernel<T, K, NQ, STAGE><<<dim3(nvb), VC::NTH, 0, c->stream>>>(
-                      qin, in, frec, out, g, ph, mu, 3LL * bpd)));
-  return DG_HGKS_OK;
-}
-
-// Reverse sweep over the steps.  Segment s covers steps [s*stride,
-// min((s+1)*stride, nsteps)); it is recomputed from its checkpoint, keeping
-// Q^n (FP64) and Q* (bulk precision) of every step, then reversed step by step:
-//   stage 2: qsbar = (dL_t/dQ at Q*)^T (dt^2/3 qbar)
-//   stage 1: qbar <- qbar + qsbar + (d(L, L_t)/dQ at Q^n)^T (dt qbar + dt/2 qsbar,
-//                                                          dt^2/6 qbar + dt^2/8 qsbar)
-template <class T, int K, int NQ>
-int run_adjoint(dg_hgks_ctx* c, const double* ckpt, int stride, double dt, int nsteps, const double* qN_bar,
-                double* q0_bar, double* mu_bar_host) {
-  const Geo g = make_geo(c->p);
-  const Phys ph = make_phys(c, dt);
-  const long long n = 5LL * c->nm * g.ncell;
-  constexpr bool bulk = sizeof(T) == 4;
-  T* qs = bulk ? (T*)(c->ws + c->lay.qs) : nullptr;
-  double* P = (double*)(c->ws + c->lay.P);
-  double* states = (double*)(c->ws + c->lay.adj_states);
-  T* stars = (T*)(c->ws + c->lay.adj_stars);
-  double* qbar = (double*)(c->ws + c->lay.adj_qbar);
-  double* qsbar = (double*)(c->ws + c->lay.adj_qsbar);
-  double* mu = (double*)(c->ws + c->lay.adj_mu);
-  double* mu_out = (double*)(c->ws + c->lay.adj_tmp);
-  const long long nslots = (long long)adj_mu_slots((size_t)g.ncell);
-  int rc = ensure_flag(c);
-  if (rc) return rc;
-  DG_HIP(c, hipMemcpyAsync(qbar, qN_bar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  DG_LAUNCH(c, 2, (zero_kernel<<<dim3(256), 256, 0, c->stream>>>(mu, nslots)));
-  const int nseg = (nsteps + stride - 1) / stride;
-  for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int n0 = seg * stride;
-    const int len = std::min(stride, nsteps - n0);
-    DG_HIP(c, hipMemcpyAsync(states, ckpt + (size_t)seg * n, n * sizeof(double), hipMemcpyDeviceToDevice,
-                             c->stream));
-    // forward recomputation of the segment
-    for (int j = 0; j < len; ++j) {
-      double* Sj = states + (size_t)j * n;
-      T* Qs = stars + (size_t)j * n;
-      const T* qin;
-      if constexpr (bulk) {
-        rc = launch_convert<T>(c, Sj, qs, n);
-        if (rc) return rc;
-        qin = qs;
-      } else {
-        qin = (const T*)Sj;
-      }
-      VolOut<T> o1{};
-      o1.qn = Sj;
-      o1.P = P;
-      o1.qstar = Qs;
-      o1.dt = dt;
-      rc = launch_stage<T, K, NQ, 0>(c, qin, o1, g, ph);
-      if (rc) return rc;
-      if (j + 1 < len) {
-        VolOut<T> o2{};
-        o2.P = P;
-        o2.qnew = states + (size_t)(j + 1) * n;
-        o2.qshadow = nullptr;
-        o2.dt = dt;
-        rc = launch_stage<T, K, NQ, 1>(c, Qs, o2, g, ph);
-        if (rc) return rc;
-      }
-    }
-    // reverse
-    for (int j = len - 1; j >= 0; --j) {
-      double* Sj = states + (size_t)j * n;
-      const T* Qs = stars + (size_t)j * n;
-      AdjIn<2> in2{qbar, qsbar, dt};
-      rc = launch_adj_stage<T, K, NQ, 2>(c, Qs, in2, qsbar, g, ph);
-      if (rc) return rc;
-      const T* qin;
-      if constexpr (bulk) {
-        rc = launch_convert<T>(c, Sj, qs, n);
-        if (rc) return rc;
-        qin = qs;
-      } else {
-        qin = (const T*)Sj;
-      }
-      AdjIn<1> in1{qbar, qsbar, dt};
-      rc = launch_adj_stage<T, K, NQ, 1>(c, qin, in1, qbar, g, ph);
-      if (rc) return rc;
-    }
-  }
-  DG_HIP(c, hipMemcpyAsync(q0_bar, qbar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<1, 256, 0, c->stream>>>(mu, nslots, mu_out)));
-  double h = 0.0;
-  DG_HIP(c, hipMemcpyAsync(&h, mu_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  DG_HIP(c, hipStreamSynchronize(c->stream));
-  *mu_bar_host = h;
-  return dg_hgks_check(c);
 }
 
 }  // namespace
@@ -478,7 +257,7 @@ int dg_hgks_step(dg_hgks_ctx* c, double* q, double dt, int32_t nsteps, double* c
   if (ckpt && ckpt_stride < 1) return fail(c, DG_HGKS_EINVAL, "ckpt_stride must be >= 1");
   return dispatch(c->p, [&](auto tag) {
     using Tg = decltype(tag);
-    return run_step<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, nsteps, ckpt, ckpt_stride);
+    return dgrt::run_step<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, nsteps, ckpt, ckpt_stride);
   });
 }
 
@@ -488,7 +267,7 @@ int dg_hgks_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, doub
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, DG_HGKS_EINVAL, "dt must be finite and > 0");
   return dispatch(c->p, [&](auto tag) {
     using Tg = decltype(tag);
-    return run_residual<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, L, Lt);
+    return dgrt::run_residual<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, L, Lt);
   });
 }
 
@@ -503,7 +282,7 @@ int dg_hgks_adjoint(dg_hgks_ctx* c, const double* ckpt, int32_t ckpt_stride, dou
     return fail(c, DG_HGKS_ENOMEM, "ckpt_stride exceeds the adjoint room of the workspace");
   return dispatch(c->p, [&](auto tag) {
     using Tg = decltype(tag);
-    return run_adjoint<typename Tg::T, Tg::K, Tg::NQ>(c, ckpt, ckpt_stride, dt, nsteps, qN_bar, q0_bar,
+    return dgrt::run_adjoint<typename Tg::T, Tg::K, Tg::NQ>(c, ckpt, ckpt_stride, dt, nsteps, qN_bar, q0_bar,
                                                        mu_bar_host);
   });
 }

@@ -452,12 +452,12 @@ __global__ __launch_bounds__(64 * NQ) void adj_volume_kernel(const T* __restrict
   block_add_mu<NTH>(mub, mu_part, slot0 + blockIdx.x, red);
 }
 
-__global__ __launch_bounds__(256) void zero_kernel(double* a, long long n) {
+static __global__ __launch_bounds__(256) void zero_kernel(double* a, long long n) {
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) a[i] = 0.0;
 }
 
 // Fixed-order sum of the dJ/dmu slots into out[0] (one block).
-__global__ __launch_bounds__(256) void reduce_mu_kernel(const double* a, long long n, double* out) {
+static __global__ __launch_bounds__(256) void reduce_mu_kernel(const double* a, long long n, double* out) {
   __shared__ double sh[256];
   double s = 0.0;
   for (long long i = threadIdx.x; i < n; i += 256) s += a[i];

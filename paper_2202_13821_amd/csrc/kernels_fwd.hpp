@@ -2,21 +2,24 @@
 //
 // Data layout in HBM (structure of arrays, x fastest):
 //   coefficients  q[var][mode][z][y][x]             (FP64 at the C-ABI; T copy inside)
-//   face records  rec[dir][cell][var][F|Ft][tmode]   one record per upper face
-//                 of each cell: the face flux projected on the tangential
-//                 Legendre modes of the face, Phi_m = sum_q w_q F(x_q) phi_m(x_q)
+//   face records  rec[dir][tile][F|Ft][var][tmode][64]  one record per upper
+//                 face of each cell (tile = cell / 64, then cell % 64): the
+//                 face flux projected on the tangential Legendre modes of the
+//                 face, Phi_m = sum_q w_q F(x_q) phi_m(x_q).  A wavefront of the
+//                 volume kernel (64 cells) reads each record component as one
+//                 contiguous row, the rows of a tile at fixed offsets.
 //
 // One stage is two launches:
 //   face_kernel   -- every face of the grid once: traces of both cells at the
 //                    face Gauss points (coefficients staged through LDS), the
 //                    gas-kinetic face flux per point, then the projection on
 //                    the tangential modes.  One lane per face point.
-//   volume_kernel -- per cell: point values and gradients at the volume Gauss
-//                    points, the volume flux per point, the projection
-//                    sum_q w_q F_d dB_n/dx_d as a dense contraction on MFMA
-//                    (v_mfma_*_16x16x4), the surface terms from the six face
-//                    records, M^{-1}, and the fused stage update with FP64
-//                    accumulation of the modal coefficients.
+//   volume_kernel -- one lane per cell: point values and gradients at the
+//                    volume Gauss points, the volume flux per point, the
+//                    projection sum_q w_q F_d dB_n/dx_d in registers, the
+//                    surface terms from the six face records, M^{-1}, and the
+//                    fused stage update with FP64 accumulation of the modal
+//                    coefficients.
 #pragma once
 
 #include "gks_point.hpp"
@@ -43,6 +46,12 @@ DGK_D unsigned nb32(unsigned c, int d, int off, const Geo& g) {
   return (off > 0) ? (k + 1 == nz ? c - k * pl : c + pl) : (k == 0 ? c + (nz - 1) * pl : c - pl);
 }
 
+// Element index of component r of the record of cell `cell` along axis d
+// (rec_len components per record, ntile = ceil(N / 64) tiles per axis).
+DGK_D long long rec_index(int d, long long cell, int r, int rec_len, long long ntile) {
+  return (((long long)d * ntile + (cell >> 6)) * rec_len + r) * 64 + (cell & 63);
+}
+
 // Runtime-indexed node value of the NQ-point rule.
 template <int NQ>
 DGK_D double gauss_x(int i) {
@@ -62,8 +71,8 @@ DGK_D double gauss_w(int i) {
 }
 
 // Tables of the volume projection: B[kk][n] = w_q dB_n/dxi_d (x_q) with
-// kk = 3 q + d, q = (qz NQ + qy) NQ + qx; rows padded to a multiple of 4 and
-// columns to 16 with zeros (MFMA operand B of a 16x16x4 tile).
+// kk = 3 q + d, q = (qz NQ + qy) NQ + qx (rows padded to a multiple of 4 and
+// columns to 16 with zeros).
 template <class T, int K, int NQ>
 struct VolTab {
   static constexpr int NM = nmodes(K);
@@ -246,18 +255,18 @@ DGK_D void face_block(const T* __restrict__ q, T* __restrict__ rec, const Geo& g
     }
   }
   __syncthreads();
-  // projection on the tangential modes: rec = sum_qf phi[m][qf] F(qf)
+  // projection on the tangential modes: rec = sum_qf phi[m][qf] F(qf); the
+  // block's faces run fastest so that each record row is written contiguously
   const auto& ft = FaceTabHolder<T, K, NQ>::t;
-  for (int o = l; o < FPW * RECN; o += 64) {
-    const int fo = w * FPW + o / RECN;
-    const int r = o % RECN;
+  for (int o = tid; o < FPB * RECN; o += 256) {
+    const int fo = o % FPB, r = o / FPB;
     const int comp = r / NT, m = r - comp * NT;  // comp = F|Ft * 5 + var  (NF = 2) or var
     const long long f = f0 + fo;
     if (f < N) {
       T s = T(0);
 #pragma unroll
       for (int k = 0; k < NQ2; ++k) s += ft.phi[m][k] * sF[fo][k][comp];
-      rec[((long long)D * N + f) * RECN + r] = s;
+      rec[rec_index(D, f, r, RECN, (N + 63) >> 6)] = s;
     }
   }
 }
@@ -289,32 +298,14 @@ __global__ __launch_bounds__(256, FaceWaves<T>::value) void face_kernel(const T*
 }
 
 // --------------------------------------------------------------------------
-// MFMA 16x16x4: D = A B + C with lane l holding A[l%16][l/16], B[l/16][l%16];
-// the four accumulator entries of lane l are rows 4 (l/16) + i (f32) or
-// l/16 + 4 i (f64) of column l%16, i = 0..3 (measured on gfx950).
-// --------------------------------------------------------------------------
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double v4d __attribute__((ext_vector_type(4)));
-template <class T>
-struct Acc;
-template <>
-struct Acc<float> {
-  using type = v4f;
-};
-template <>
-struct Acc<double> {
-  using type = v4d;
-};
-DGK_D v4f mfma16x16x4(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-DGK_D v4d mfma16x16x4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-template <class T>
-DGK_D int mfma_row(int lk, int i) {
-  return sizeof(T) == 4 ? 4 * lk + i : lk + 4 * i;
-}
-
-// --------------------------------------------------------------------------
-// Volume kernel.  Block = NQ wavefronts and CPB = 64/NQ^2 cells; wavefront w
-// evaluates the points with z-index w, one lane per point.
+// Volume kernel.  One lane per cell, 256 cells per block; every lane of a
+// wavefront visits the same volume point at the same time, so the basis
+// values of the point are wavefront-uniform (scalar loads).  Per point: the
+// trace Q, dQ from the cell's coefficients (registers), the volume flux, and
+// its projection sum_q w_q F_d dB_n/dx_d accumulated in registers over the
+// non-zero entries of dB_n/dxi_d.  Then the six face records of the cell
+// (record layout rec[dir][component][cell]: one coalesced row per component),
+// M^{-1}, and the stage update in FP64.
 // MODE 0: stage 1 (F and Ft)   -> Q* (T) and P = Q^n + dt L + dt^2/6 L_t (FP64)
 // MODE 1: stage 2 (Ft only)    -> Q^{n+1} = P + dt^2/3 L_t(Q*) (FP64, + T copy)
 // MODE 2: operator only        -> L, L_t (FP64)
@@ -331,6 +322,8 @@ struct VolOut {
   double dt;
 };
 
+// Blocking of the adjoint volume kernel: CPB = 64/NQ^2 cells, NQ wavefronts,
+// one lane per volume point.
 template <int K, int NQ>
 struct VolCfg {
   static constexpr int NM = nmodes(K), NT = ntan(K), NQ2 = NQ * NQ, NQ3 = NQ * NQ * NQ;
@@ -339,180 +332,182 @@ struct VolCfg {
   static constexpr int CS = 5 * NM + 1;
 };
 
+// Cell-per-lane kernels: 4 wavefronts per block; minimum waves per SIMD
+// requested from the register allocator (FP32: two resident wavefronts per
+// SIMD hide the memory phases; FP64 needs twice the registers).
+constexpr int kCellThreads = 256;
+template <class T>
+struct CellWaves {
+  static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
+
+// Basis at the volume points, q = (qz NQ + qy) NQ + qx: phi[q][n] = B_n(x_q),
+// dphi[q][d][n] = dB_n/dxi_d (x_q) (reference coordinates), w[q] = product
+// of the Gauss weights (summing to 1).
+template <class T, int K, int NQ>
+struct PointBasis {
+  static constexpr int NM = nmodes(K), NQ3 = NQ * NQ * NQ;
+  T phi[NQ3][NM];
+  T dphi[NQ3][3][NM];
+  T w[NQ3];
+  constexpr PointBasis() : phi{}, dphi{}, w{} {
+    constexpr Modes<K> md{};
+    for (int q = 0; q < NQ3; ++q) {
+      const int ix[3] = {q % NQ, (q / NQ) % NQ, q / (NQ * NQ)};
+      const double x[3] = {Gauss<NQ>::x[ix[0]], Gauss<NQ>::x[ix[1]], Gauss<NQ>::x[ix[2]]};
+      w[q] = T(Gauss<NQ>::w[ix[0]] * Gauss<NQ>::w[ix[1]] * Gauss<NQ>::w[ix[2]]);
+      for (int n = 0; n < NM; ++n) {
+        phi[q][n] = T(leg(md.e[n][0], x[0]) * leg(md.e[n][1], x[1]) * leg(md.e[n][2], x[2]));
+        for (int d = 0; d < 3; ++d) {
+          double v = 1.0;
+          for (int e = 0; e < 3; ++e) v *= (e == d) ? dleg(md.e[n][e], x[e]) : leg(md.e[n][e], x[e]);
+          dphi[q][d][n] = T(v);
+        }
+      }
+    }
+  }
+};
+template <class T, int K, int NQ>
+struct PointBasisHolder {
+  static constexpr PointBasis<T, K, NQ> t{};
+};
+
+// Block order for the 8 XCDs: the hardware hands consecutive block indices to
+// the XCDs in turn; this bijection of [0, nb) gives XCD x (= b mod 8) one
+// contiguous range of logical blocks, so that neighbouring cells (and the face
+// records they share) stay in one XCD's L2.
+DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b & 7u, q = nb >> 3, r = nb & 7u;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 template <class T, int K, int NQ, int MODE>
-__global__ __launch_bounds__(64 * NQ) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec, Geo g,
-                                                        Phys ph, VolOut<T> out, int* flag) {
-  using C = VolCfg<K, NQ>;
-  constexpr int NM = C::NM, NT = C::NT, NQ2 = C::NQ2, CPB = C::CPB, NW = C::NW, NTH = C::NTH;
-  constexpr int KK = C::KK, KS = C::KS;
+__global__ __launch_bounds__(kCellThreads, CellWaves<T>::value) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,
+                                                             Geo g, Phys ph, VolOut<T> out, int* flag) {
+  constexpr int NM = nmodes(K), NT = ntan(K), NQ3 = NQ * NQ * NQ;
   constexpr bool NEED_F = (MODE != 1);
   constexpr int NF = NEED_F ? 2 : 1;
-  constexpr int NR = CPB * 5 * NF;  // rows of the projection: (cell, var, F|Ft)
-  constexpr int NRT = (NR + 15) / 16;
   constexpr int RECN = 5 * NF * NT;
-  // sA holds the MFMA operand, then the block's face records
-  constexpr int NRA = (NR * KK >= 6 * CPB * RECN) ? NR : (6 * CPB * RECN + KK - 1) / KK;
-  __shared__ T sq[CPB][C::CS];
-  __shared__ T sA[NRA][KK];
-  __shared__ T sR[NR][NM];
-  const int tid = threadIdx.x;
+  constexpr Modes<K> md{};
   const long long N = g.ncell;
-  const long long c0 = (long long)blockIdx.x * CPB;
+  const long long c = (long long)xcd_block(blockIdx.x, gridDim.x) * kCellThreads + threadIdx.x;
+  const bool act = c < N;
+  const long long cc = act ? c : N - 1;  // lanes past the end recompute the last cell, store nothing
 
-  for (int idx = tid; idx < CPB * 5 * NM; idx += NTH) {
-    const int vm = idx / CPB, j = idx - vm * CPB;
-    if (c0 + j < N) sq[j][vm] = q[(long long)vm * N + c0 + j];
-  }
-  __syncthreads();
+  T cf[5][NM];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int n = 0; n < NM; ++n) cf[v][n] = q[(long long)(v * NM + n) * N + cc];
 
-  const int w = tid >> 6, l = tid & 63;
-  const int cl = l / NQ2, qxy = l % NQ2;
-  if (cl < CPB) {
-    const int qx = qxy % NQ, qy = qxy / NQ, qz = w;
-    const int qi = (qz * NQ + qy) * NQ + qx;
-    T F[3][5], Ft[3][5];
-    if (c0 + cl < N) {
-      const double x[3] = {gauss_x<NQ>(qx), gauss_x<NQ>(qy), gauss_x<NQ>(qz)};
-      T P[3][K + 1], dP[3][K + 1];
+  // acc[f][v][n] = sum_q w_q sum_d F^f_d[v](x_q) (2/dx_d) dB_n/dxi_d (x_q), f = F | Ft
+  T acc[NF][5][NM];
 #pragma unroll
-      for (int e = 0; e < 3; ++e)
-#pragma unroll
-        for (int i = 0; i <= K; ++i) {
-          P[e][i] = T(leg(i, x[e]));
-          dP[e][i] = T(dleg(i, x[e]));
-        }
-      T Q[5], dQ[3][5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const T* c = &sq[cl][v * NM];
-        T v0 = T(0), vx = T(0), vy = T(0), vz = T(0);
-        static_for<NM>([&](auto nc) {
-          constexpr int n = decltype(nc)::value;
-          constexpr Modes<K> md{};
-          constexpr int a = md.e[n][0], b = md.e[n][1], e = md.e[n][2];
-          const T cn = c[n];
-          v0 += cn * (P[0][a] * P[1][b] * P[2][e]);
-          if constexpr (a > 0) vx += cn * (dP[0][a] * P[1][b] * P[2][e]);
-          if constexpr (b > 0) vy += cn * (P[0][a] * dP[1][b] * P[2][e]);
-          if constexpr (e > 0) vz += cn * (P[0][a] * P[1][b] * dP[2][e]);
-        });
-        Q[v] = v0;
-        dQ[0][v] = vx * T(g.two_inv_dx[0]);
-        dQ[1][v] = vy * T(g.two_inv_dx[1]);
-        dQ[2][v] = vz * T(g.two_inv_dx[2]);
-      }
-      int bad = 0;
-      volume_flux<T, NEED_F>(ph, Q, dQ, F, Ft, bad);
-      if (bad) atomicOr(flag, 1);
-    } else {
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) F[d][v] = Ft[d][v] = T(0);
-    }
+  for (int f = 0; f < NF; ++f)
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
+      for (int n = 0; n < NM; ++n) acc[f][v][n] = T(0);
+  const T sc[3] = {T(g.two_inv_dx[0]), T(g.two_inv_dx[1]), T(g.two_inv_dx[2])};
+  using PB = PointBasisHolder<T, K, NQ>;
+  int bad = 0;
+#pragma unroll 1
+  for (int qi = 0; qi < NQ3; ++qi) {
+    // physical-space derivative of the basis at this point (uniform)
+    T ds[3][NM];
+    static_for<NM>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) ds[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] * sc[d] : T(0);
+    });
+    T Q[5], dQ[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T v0 = T(0), vx = T(0), vy = T(0), vz = T(0);
+      static_for<NM>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        const T cn = cf[v][n];
+        v0 += cn * PB::t.phi[qi][n];
+        if constexpr (md.e[n][0] > 0) vx += cn * ds[0][n];
+        if constexpr (md.e[n][1] > 0) vy += cn * ds[1][n];
+        if constexpr (md.e[n][2] > 0) vz += cn * ds[2][n];
+      });
+      Q[v] = v0;
+      dQ[0][v] = vx;
+      dQ[1][v] = vy;
+      dQ[2][v] = vz;
+    }
+    T F[3][5], Ft[3][5];
+    volume_flux<T, NEED_F>(ph, Q, dQ, F, Ft, bad);
+    const T wq = PB::t.w[qi];
+    static_for<NM>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const T s = T(g.two_inv_dx[d]);
-        if constexpr (NEED_F) {
-          sA[(cl * 5 + v) * 2 + 0][3 * qi + d] = F[d][v] * s;
-          sA[(cl * 5 + v) * 2 + 1][3 * qi + d] = Ft[d][v] * s;
-        } else {
-          sA[cl * 5 + v][3 * qi + d] = Ft[d][v] * s;
+        if (md.e[n][d] > 0) {
+          const T b = ds[d][n] * wq;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            if constexpr (NEED_F) acc[0][v][n] += F[d][v] * b;
+            acc[NF - 1][v][n] += Ft[d][v] * b;
+          }
         }
       }
+    });
   }
-  __syncthreads();
+  if (bad && act) atomicOr(flag, 1);
 
-  // volume projection on MFMA: sR[row][n] = sum_kk sA[row][kk] B[kk][n]
-  {
-    const auto& bt = VolTabHolder<T, K, NQ>::t;
-    const int lr = l & 15, lk = l >> 4;
-    for (int tile = w; tile < NRT; tile += NW) {
-      typename Acc<T>::type acc = {0, 0, 0, 0};
-      const int row = tile * 16 + lr;
-#pragma unroll 4
-      for (int s = 0; s < KS; ++s) {
-        const int kk = 4 * s + lk;
-        const T a = (row < NR && kk < KK) ? sA[row][kk] : T(0);
-        const T b = bt.B[kk][lr];
-        acc = mfma16x16x4(a, b, acc);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = tile * 16 + mfma_row<T>(lk, i);
-        if (r < NR && lr < NM) sR[r][lr] = acc[i];
-      }
-    }
-  }
-  __syncthreads();
-
-  // face records of the block's cells, staged through LDS with coalesced
-  // loads (the MFMA operand space is free now): sRec[d][0][j] = upper face of
-  // cell j, sRec[d][1][j] = its lower face (upper face of the cell below).
-  static_assert(6 * CPB * RECN <= NRA * KK, "face records must fit in sA");
-  T(*sRec)[2][CPB][RECN] = reinterpret_cast<T(*)[2][CPB][RECN]>(&sA[0][0]);
-  __shared__ unsigned sdn[3][CPB];
-  if (tid < 3 * CPB) {
-    const int d = tid / CPB, j = tid % CPB;
-    if (c0 + j < N) sdn[d][j] = nb32(unsigned(c0 + j), d, -1, g);
-  }
-  __syncthreads();
-  for (int idx = tid; idx < 6 * CPB * RECN; idx += NTH) {
-    const int r = idx % RECN, t = idx / RECN;
-    const int j = t % CPB, ds = t / CPB;  // ds = d * 2 + side
-    const int d = ds >> 1, side = ds & 1;
-    const long long c = c0 + j;
-    if (c < N) {
-      const long long cf = side ? (long long)sdn[d][j] : c;
-      sRec[d][side][j][r] = rec[((long long)d * N + cf) * RECN + r];
-    }
-  }
-  __syncthreads();
-
-  // surface terms, M^{-1} and the stage update; item = (var, mode, cell), cell fastest
+  // surface terms: the upper face of the cell (its own record) minus the
+  // lower face (record of the neighbour below) with the parity sign of B_n at
+  // xi_d = -1, added to the volume term in T (a difference of two nearby
+  // records is exact in T); M^{-1} and the stage update in FP64.
   const auto& mt = ModeTabHolder<K>::t;
-  for (int it = tid; it < CPB * 5 * NM; it += NTH) {
-    const int j = it % CPB, vm = it / CPB;
-    const int v = vm / NM, n = vm - v * NM;
-    const long long c = c0 + j;
-    if (c >= N) continue;
-    double Lt = double(sR[(j * 5 + v) * NF + NF - 1][n]);
-    double L = NEED_F ? double(sR[(j * 5 + v) * NF][n]) : 0.0;
+  const long long ntile = (N + 63) >> 6;
+  static_for<3>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    const T ix = T(g.inv_dx[d]);
+    const T* pu = rec + rec_index(d, cc, 0, RECN, ntile);
+    const T* pl = rec + rec_index(d, (long long)nb32(unsigned(cc), d, -1, g), 0, RECN, ntile);
+    static_for<NF>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int m = mt.tm[n][d];
-      const double sg = (mt.nd[n][d] & 1) ? -1.0 : 1.0;
-      const T* ru = sRec[d][0][j];
-      const T* rl = sRec[d][1][j];
-      if constexpr (NEED_F) {
-        const int of = v * NT + m;
-        const int oft = (5 + v) * NT + m;
-        L += g.inv_dx[d] * (sg * double(rl[of]) - double(ru[of]));
-        Lt += g.inv_dx[d] * (sg * double(rl[oft]) - double(ru[oft]));
+      for (int v = 0; v < 5; ++v) {
+        static_for<NT>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          const int r = (f * 5 + v) * NT + m;
+          const T ru = pu[r * 64], rl = pl[r * 64];
+          const T dm = ix * (rl - ru), dp = -ix * (rl + ru);
+          static_for<NM>([&](auto nc) {
+            constexpr int n = decltype(nc)::value;
+            if constexpr (face_tan_of_mode<K>(n, d) == m) acc[f][v][n] += (md.e[n][d] & 1) ? dp : dm;
+          });
+        });
+      }
+    });
+  });
+  if (!act) return;
+  const double dt = out.dt;
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int n = 0; n < NM; ++n) {
+      const double mi = mt.minv[n];
+      const double Ln = NEED_F ? double(acc[0][v][n]) * mi : 0.0;
+      const double Ltn = double(acc[NF - 1][v][n]) * mi;
+      const long long gi = (long long)(v * NM + n) * N + c;
+      if constexpr (MODE == 0) {
+        const double qn = out.qn[gi];
+        out.qstar[gi] = T(qn + 0.5 * dt * Ln + 0.125 * dt * dt * Ltn);
+        out.P[gi] = qn + dt * Ln + (dt * dt / 6.0) * Ltn;
+      } else if constexpr (MODE == 1) {
+        const double qnew = out.P[gi] + (dt * dt / 3.0) * Ltn;
+        out.qnew[gi] = qnew;
+        if (out.qshadow) out.qshadow[gi] = T(qnew);
       } else {
-        const int ot = v * NT + m;
-        Lt += g.inv_dx[d] * (sg * double(rl[ot]) - double(ru[ot]));
+        out.L[gi] = Ln;
+        out.Lt[gi] = Ltn;
       }
     }
-    L *= mt.minv[n];
-    Lt *= mt.minv[n];
-    const long long gi = (long long)vm * N + c;
-    const double dt = out.dt;
-    if constexpr (MODE == 0) {
-      const double qn = out.qn[gi];
-      out.qstar[gi] = T(qn + 0.5 * dt * L + 0.125 * dt * dt * Lt);
-      out.P[gi] = qn + dt * L + (dt * dt / 6.0) * Lt;
-    } else if constexpr (MODE == 1) {
-      const double qnew = out.P[gi] + (dt * dt / 3.0) * Lt;
-      out.qnew[gi] = qnew;
-      if (out.qshadow) out.qshadow[gi] = T(qnew);
-    } else {
-      out.L[gi] = L;
-      out.Lt[gi] = Lt;
-    }
-  }
 }
 
 // FP64 -> T copy of the coefficients (stage-1 input of the bulk-precision path).

@@ -6,8 +6,9 @@ LLVM IR (common subexpressions merged, loops unrolled; the code is straight
 line) and their IR instructions are counted: fadd/fsub/fmul = 1 flop,
 llvm.fmuladd/llvm.fma = 2, fdiv = 1, sqrt/exp/erfc = 1 each (also listed
 apart).  The modal evaluation at the point and the projection onto the modes
-are dense contractions whose useful flops are added in closed form (P2, 3
-Gauss points per direction, 10 modes, 6 tangential modes).
+are contractions whose useful flops (non-zero basis entries only) are added
+in closed form (P2, 3 Gauss points per direction, 10 modes, 6 tangential
+modes, 4 modes with a non-zero derivative along each axis).
 """
 import json
 import os
@@ -82,8 +83,9 @@ def main():
             vol = count(text, f"fc_vol_{T}_{st}")
             # face: two traces, flux, projection on NT tangential modes (per point share)
             face_total = 2 * eval_pt + face["flops"] + nf * 5 * NT * 2
-            # volume: one evaluation, flux, projection sum_q w F_d dB_n (NM modes, 3 directions)
-            vol_total = eval_pt + vol["flops"] + nf * 5 * 3 * NM * 2
+            # volume: one evaluation, flux, projection sum_q w F_d dB_n/dx_d over the
+            # 3 nd non-zero (d, n) entries
+            vol_total = eval_pt + vol["flops"] + nf * 5 * 3 * nd * 2
             d[f"face_stage{st[1]}"] = face_total
             d[f"volume_stage{st[1]}"] = vol_total
             d[f"face_point_flux_stage{st[1]}_detail"] = face

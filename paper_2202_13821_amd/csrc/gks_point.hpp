@@ -103,23 +103,9 @@ DGK_HD bool unphysical(const Prim<T>& s) {
   return !(s.rho > T(0)) || !(s.p > T(0)) || !d_finite(s.U + s.V + s.W + s.p);
 }
 
-// Normalised one-dimensional moments <c^0..c^6> plus <xi^2>, <xi^4>.
-template <class T>
-struct Mom {
-  T u[7], v[7], w[7], x2, x4;
-};
-
-// <c^{n+2}> = U <c^{n+1}> + (n+1) th <c^n>  (Gaussian integration by parts)
-template <class T>
-DGK_HD void mom_full(T U, T th, T* m) {
-  m[0] = T(1);
-  m[1] = U;
-#pragma unroll
-  for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + T(n + 1) * th * m[n];
-}
-
-// Half line u > 0 (side > 0) or u < 0: first two moments from erfc and the
-// Gaussian at u = 0, then the same recurrence.
+// Moments <u^n>, n = 0..6, of the normalised Maxwellian in u over the half
+// line u > 0 (side > 0) or u < 0: the first two from erfc and the Gaussian at
+// u = 0, then <u^{n+2}> = U <u^{n+1}> + (n+1) th <u^n> (integration by parts).
 template <class T>
 DGK_HD void mom_half(T U, T th, int side, T* m) {
   const T r = d_rsqrt(T(2) * th);  // sqrt(lambda)
@@ -135,71 +121,6 @@ DGK_HD void mom_half(T U, T th, int side, T* m) {
   }
 #pragma unroll
   for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + T(n + 1) * th * m[n];
-}
-
-template <class T>
-DGK_HD void mom_xi(T K, T th, Mom<T>& t) {
-  t.x2 = K * th;
-  t.x4 = K * (K + T(2)) * th * th;
-}
-
-template <class T>
-DGK_HD Mom<T> moments_full(const Prim<T>& s, T K) {
-  Mom<T> t;
-  mom_full(s.U, s.th, t.u);
-  mom_full(s.V, s.th, t.v);
-  mom_full(s.W, s.th, t.w);
-  mom_xi(K, s.th, t);
-  return t;
-}
-
-// Tangential tables of a half-space set are the full ones; only u differs.
-template <class T>
-DGK_HD Mom<T> moments_half(const Prim<T>& s, const Mom<T>& full, int side) {
-  Mom<T> t = full;
-  mom_half(s.U, s.th, side, t.u);
-  return t;
-}
-
-// <u^a v^b w^c (xi^2)^d>
-template <int a, int b, int c, int d, class T>
-DGK_HD T Mo(const Mom<T>& t) {
-  static_assert(a <= 6 && b <= 6 && c <= 6 && d <= 2, "moment order");
-  T r = t.u[a];
-  if constexpr (b > 0) r *= t.v[b];
-  if constexpr (c > 0) r *= t.w[c];
-  if constexpr (d == 1) r *= t.x2;
-  if constexpr (d == 2) r *= t.x4;
-  return r;
-}
-
-// <u^a v^b w^c (xi^2)^d  s>, s = sum_j s_j psi_j
-template <int a, int b, int c, int d, class T>
-DGK_HD T Gs(const Mom<T>& t, const T s[5]) {
-  return s[0] * Mo<a, b, c, d>(t) + s[1] * Mo<a + 1, b, c, d>(t) + s[2] * Mo<a, b + 1, c, d>(t) +
-         s[3] * Mo<a, b, c + 1, d>(t) +
-         T(0.5) * s[4] * (Mo<a + 2, b, c, d>(t) + Mo<a, b + 2, c, d>(t) + Mo<a, b, c + 2, d>(t) + Mo<a, b, c, d + 1>(t));
-}
-
-// out_k = <u^a v^b w^c s psi_k>
-template <int a, int b, int c, class T>
-DGK_HD void Gpsi(const Mom<T>& t, const T s[5], T out[5]) {
-  out[0] = Gs<a, b, c, 0>(t, s);
-  out[1] = Gs<a + 1, b, c, 0>(t, s);
-  out[2] = Gs<a, b + 1, c, 0>(t, s);
-  out[3] = Gs<a, b, c + 1, 0>(t, s);
-  out[4] = T(0.5) * (Gs<a + 2, b, c, 0>(t, s) + Gs<a, b + 2, c, 0>(t, s) + Gs<a, b, c + 2, 0>(t, s) +
-                     Gs<a, b, c, 1>(t, s));
-}
-
-// out_k = <u^a v^b w^c psi_k>
-template <int a, int b, int c, class T>
-DGK_HD void psim(const Mom<T>& t, T out[5]) {
-  out[0] = Mo<a, b, c, 0>(t);
-  out[1] = Mo<a + 1, b, c, 0>(t);
-  out[2] = Mo<a, b + 1, c, 0>(t);
-  out[3] = Mo<a, b, c + 1, 0>(t);
-  out[4] = T(0.5) * (Mo<a + 2, b, c, 0>(t) + Mo<a, b + 2, c, 0>(t) + Mo<a, b, c + 2, 0>(t) + Mo<a, b, c, 1>(t));
 }
 
 // Closed-form solution of <a psi> = b for the Maxwellian (U, V, W, th):

@@ -52,13 +52,6 @@ DGK_HD void prim_bwd(const T Q[5], const Prim<T>& s, Prim<T> sb, T gm1, T Qb[5])
 }
 
 // ---- moment tables ------------------------------------------------------------
-template <class T>
-DGK_HD void mom_zero(Mom<T>& b) {
-#pragma unroll
-  for (int i = 0; i < 7; ++i) b.u[i] = b.v[i] = b.w[i] = T(0);
-  b.x2 = b.x4 = T(0);
-}
-
 // m_{n+2} = U m_{n+1} + (n+1) th m_n, n = 0..4, from m_0, m_1.
 template <class T>
 DGK_HD void mom_rec_bwd(T U, T th, const T* m, T* mb, T& Ub, T& thb) {
@@ -70,12 +63,6 @@ DGK_HD void mom_rec_bwd(T U, T th, const T* m, T* mb, T& Ub, T& thb) {
     mb[n] += T(n + 1) * th * g;
     thb += T(n + 1) * m[n] * g;
   }
-}
-
-template <class T>
-DGK_HD void mom_full_bwd(T U, T th, const T* m, T* mb, T& Ub, T& thb) {
-  mom_rec_bwd(U, th, m, mb, Ub, thb);
-  Ub += mb[1];  // m_1 = U; m_0 = 1 is constant
 }
 
 template <class T>
@@ -104,72 +91,6 @@ DGK_HD void mom_half_bwd(T U, T th, int side, const T* m, T* mb, T& Ub, T& thb) 
   thb -= rb * r * r * r;
 }
 
-template <class T>
-DGK_HD void mom_xi_bwd(T K, T th, const Mom<T>& tb, T& thb) {
-  thb += tb.x2 * K + tb.x4 * T(2) * K * (K + T(2)) * th;
-}
-
-// Mo<a,b,c,d> = u[a] v[b] w[c] x[d]
-template <int a, int b, int c, int d, class T>
-DGK_HD void Mo_bwd(const Mom<T>& t, T g, Mom<T>& tb) {
-  T fv = T(1), fw = T(1), fx = T(1);
-  if constexpr (b > 0) fv = t.v[b];
-  if constexpr (c > 0) fw = t.w[c];
-  if constexpr (d == 1) fx = t.x2;
-  if constexpr (d == 2) fx = t.x4;
-  const T ua = t.u[a];
-  tb.u[a] += g * fv * fw * fx;
-  if constexpr (b > 0) tb.v[b] += g * ua * fw * fx;
-  if constexpr (c > 0) tb.w[c] += g * ua * fv * fx;
-  if constexpr (d == 1) tb.x2 += g * ua * fv * fw;
-  if constexpr (d == 2) tb.x4 += g * ua * fv * fw;
-}
-
-template <int a, int b, int c, int d, class T>
-DGK_HD void Gs_bwd(const Mom<T>& t, const T s[5], T g, Mom<T>& tb, T sb[5]) {
-  sb[0] += g * Mo<a, b, c, d>(t);
-  sb[1] += g * Mo<a + 1, b, c, d>(t);
-  sb[2] += g * Mo<a, b + 1, c, d>(t);
-  sb[3] += g * Mo<a, b, c + 1, d>(t);
-  sb[4] += g * T(0.5) * (Mo<a + 2, b, c, d>(t) + Mo<a, b + 2, c, d>(t) + Mo<a, b, c + 2, d>(t) + Mo<a, b, c, d + 1>(t));
-  Mo_bwd<a, b, c, d>(t, g * s[0], tb);
-  Mo_bwd<a + 1, b, c, d>(t, g * s[1], tb);
-  Mo_bwd<a, b + 1, c, d>(t, g * s[2], tb);
-  Mo_bwd<a, b, c + 1, d>(t, g * s[3], tb);
-  const T h = T(0.5) * g * s[4];
-  Mo_bwd<a + 2, b, c, d>(t, h, tb);
-  Mo_bwd<a, b + 2, c, d>(t, h, tb);
-  Mo_bwd<a, b, c + 2, d>(t, h, tb);
-  Mo_bwd<a, b, c, d + 1>(t, h, tb);
-}
-
-template <int a, int b, int c, class T>
-DGK_HD void Gpsi_bwd(const Mom<T>& t, const T s[5], const T ob[5], Mom<T>& tb, T sb[5]) {
-  Gs_bwd<a, b, c, 0>(t, s, ob[0], tb, sb);
-  Gs_bwd<a + 1, b, c, 0>(t, s, ob[1], tb, sb);
-  Gs_bwd<a, b + 1, c, 0>(t, s, ob[2], tb, sb);
-  Gs_bwd<a, b, c + 1, 0>(t, s, ob[3], tb, sb);
-  const T h = T(0.5) * ob[4];
-  Gs_bwd<a + 2, b, c, 0>(t, s, h, tb, sb);
-  Gs_bwd<a, b + 2, c, 0>(t, s, h, tb, sb);
-  Gs_bwd<a, b, c + 2, 0>(t, s, h, tb, sb);
-  Gs_bwd<a, b, c, 1>(t, s, h, tb, sb);
-}
-
-template <int a, int b, int c, class T>
-DGK_HD void psim_bwd(const Mom<T>& t, const T ob[5], Mom<T>& tb) {
-  Mo_bwd<a, b, c, 0>(t, ob[0], tb);
-  Mo_bwd<a + 1, b, c, 0>(t, ob[1], tb);
-  Mo_bwd<a, b + 1, c, 0>(t, ob[2], tb);
-  Mo_bwd<a, b, c + 1, 0>(t, ob[3], tb);
-  const T h = T(0.5) * ob[4];
-  Mo_bwd<a + 2, b, c, 0>(t, h, tb);
-  Mo_bwd<a, b + 2, c, 0>(t, h, tb);
-  Mo_bwd<a, b, c + 2, 0>(t, h, tb);
-  Mo_bwd<a, b, c, 1>(t, h, tb);
-}
-
-// ---- closed-form 5x5 solve --------------------------------------------------------
 template <class T>
 struct Solver5Bar {
   T U, V, W, ith, E, c4;
@@ -474,15 +395,192 @@ DGK_HD void volume_flux_vjp(const Phys& ph, const T q[5], const T dq[3][5], cons
 }
 
 // ---- face flux ------------------------------------------------------------------------------
+// ---- reverse of the moment-matrix form of face_side -------------------------
+// Cotangents of the Transverse members (V, W enter the matrices directly too).
 template <class T>
-DGK_HD void face_acc_zero_bar(FaceAcc<T>& a) {
-  face_acc_zero(a);
+struct TransverseBar {
+  T V, W, v2, w2, v3, w3, R1, R2, vr, wr, v2r, w2r, vwr, vr2, wr2;
+};
+template <class T>
+DGK_HD TransverseBar<T> transverse_bar_zero() {
+  TransverseBar<T> b;
+  b.V = b.W = b.v2 = b.w2 = b.v3 = b.w3 = b.R1 = b.R2 = b.vr = b.wr = b.v2r = b.w2r = b.vwr = b.vr2 = b.wr2 = T(0);
+  return b;
 }
 
-// Reverse of face_side: accb holds the cotangents of the accumulators.
+// Given the member cotangents, add those of V, W, th.  The one-dimensional
+// Gaussian moments v_n = <v^n> obey dv_n/dV = n v_{n-1} and
+// dv_n/dth = n(n-1)/2 v_{n-2}; s1 = K th, s2 = K (K + 2) th^2.
+template <class T>
+DGK_HD void transverse_bwd(const Transverse<T>& t, T th, T K, const TransverseBar<T>& b, T& Vb, T& Wb, T& thb) {
+  const T V = t.V, W = t.W;
+  const T t2 = th * th;
+  const T v4 = V * V * (V * V + T(6) * th) + T(3) * t2;
+  const T w4 = W * W * (W * W + T(6) * th) + T(3) * t2;
+  const T s1 = K * th, s2 = K * (K + T(2)) * t2;
+  const T v2 = t.v2, w2 = t.w2, v3 = t.v3, w3 = t.w3;
+  T bv2 = b.v2, bw2 = b.w2, bv3 = b.v3, bw3 = b.w3, bv4 = T(0), bw4 = T(0), bv5 = T(0), bw5 = T(0);
+  T bs1 = T(0), bs2 = T(0);
+  T bV = b.V, bW = b.W;
+  // wr2 = w5 + 2 w3 (v2 + s1) + W (v4 + s2 + 2 v2 s1)
+  {
+    const T g = b.wr2;
+    bw5 += g;
+    bw3 += T(2) * (v2 + s1) * g;
+    bv2 += (T(2) * w3 + T(2) * W * s1) * g;
+    bs1 += (T(2) * w3 + T(2) * W * v2) * g;
+    bW += (v4 + s2 + T(2) * v2 * s1) * g;
+    bv4 += W * g;
+    bs2 += W * g;
+  }
+  // vr2 = v5 + 2 v3 (w2 + s1) + V (w4 + s2 + 2 w2 s1)
+  {
+    const T g = b.vr2;
+    bv5 += g;
+    bv3 += T(2) * (w2 + s1) * g;
+    bw2 += (T(2) * v3 + T(2) * V * s1) * g;
+    bs1 += (T(2) * v3 + T(2) * V * w2) * g;
+    bV += (w4 + s2 + T(2) * w2 * s1) * g;
+    bw4 += V * g;
+    bs2 += V * g;
+  }
+  // vwr = v3 W + V w3 + V W s1
+  {
+    const T g = b.vwr;
+    bv3 += W * g;
+    bW += (v3 + V * s1) * g;
+    bV += (w3 + W * s1) * g;
+    bw3 += V * g;
+    bs1 += V * W * g;
+  }
+  // w2r = w4 + w2 (v2 + s1), v2r = v4 + v2 (w2 + s1)
+  bw4 += b.w2r;
+  bw2 += (v2 + s1) * b.w2r;
+  bv2 += w2 * b.w2r;
+  bs1 += w2 * b.w2r;
+  bv4 += b.v2r;
+  bv2 += (w2 + s1) * b.v2r;
+  bw2 += v2 * b.v2r;
+  bs1 += v2 * b.v2r;
+  // wr = w3 + W (v2 + s1), vr = v3 + V (w2 + s1)
+  bw3 += b.wr;
+  bW += (v2 + s1) * b.wr;
+  bv2 += W * b.wr;
+  bs1 += W * b.wr;
+  bv3 += b.vr;
+  bV += (w2 + s1) * b.vr;
+  bw2 += V * b.vr;
+  bs1 += V * b.vr;
+  // R2 = v4 + w4 + s2 + 2 v2 w2 + 2 (v2 + w2) s1, R1 = v2 + w2 + s1
+  bv4 += b.R2;
+  bw4 += b.R2;
+  bs2 += b.R2;
+  bv2 += (T(2) * w2 + T(2) * s1) * b.R2 + b.R1;
+  bw2 += (T(2) * v2 + T(2) * s1) * b.R2 + b.R1;
+  bs1 += T(2) * (v2 + w2) * b.R2 + b.R1;
+  // the one-dimensional moments
+  Vb += bV + T(2) * V * bv2 + T(3) * v2 * bv3 + T(4) * v3 * bv4 + T(5) * v4 * bv5;
+  Wb += bW + T(2) * W * bw2 + T(3) * w2 * bw3 + T(4) * w3 * bw4 + T(5) * w4 * bw5;
+  thb += bv2 + T(3) * V * bv3 + T(6) * v2 * bv4 + T(10) * v3 * bv5;
+  thb += bw2 + T(3) * W * bw3 + T(6) * w2 * bw4 + T(10) * w3 * bw5;
+  thb += K * bs1 + T(2) * K * (K + T(2)) * th * bs2;
+}
+
+// Reverse of mat_H<P>: add the cotangents of M[P..P+4] and of the members.
+template <int P, class T>
+DGK_HD void mat_H_bwd(const T* M, const Transverse<T>& t, const T Hb[15], T* Mb, TransverseBar<T>& tb) {
+  const T h = T(0.5), q = T(0.25);
+  Mb[P] += Hb[0] + t.V * Hb[2] + t.W * Hb[3] + h * t.R1 * Hb[4] + t.v2 * Hb[9] + t.V * t.W * Hb[10] +
+           h * t.vr * Hb[11] + t.w2 * Hb[12] + h * t.wr * Hb[13] + q * t.R2 * Hb[14];
+  Mb[P + 1] += Hb[1] + t.V * Hb[6] + t.W * Hb[7] + h * t.R1 * Hb[8];
+  Mb[P + 2] += h * Hb[4] + Hb[5] + h * t.V * Hb[11] + h * t.W * Hb[13] + h * t.R1 * Hb[14];
+  Mb[P + 3] += h * Hb[8];
+  Mb[P + 4] += q * Hb[14];
+  tb.V += M[P] * Hb[2] + M[P + 1] * Hb[6] + t.W * M[P] * Hb[10] + h * M[P + 2] * Hb[11];
+  tb.W += M[P] * Hb[3] + M[P + 1] * Hb[7] + t.V * M[P] * Hb[10] + h * M[P + 2] * Hb[13];
+  tb.R1 += h * (M[P] * Hb[4] + M[P + 1] * Hb[8] + M[P + 2] * Hb[14]);
+  tb.v2 += M[P] * Hb[9];
+  tb.w2 += M[P] * Hb[12];
+  tb.vr += h * M[P] * Hb[11];
+  tb.wr += h * M[P] * Hb[13];
+  tb.R2 += q * M[P] * Hb[14];
+}
+
+template <class T>
+DGK_HD void mat_Gv_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb, TransverseBar<T>& tb) {
+  const T h = T(0.5), q = T(0.25), VW = t.V * t.W;
+  Mb[1] += t.V * Gb[0] + t.v2 * Gb[2] + VW * Gb[3] + h * t.vr * Gb[4] + t.v3 * Gb[9] + t.v2 * t.W * Gb[10] +
+           h * t.v2r * Gb[11] + t.V * t.w2 * Gb[12] + h * t.vwr * Gb[13] + q * t.vr2 * Gb[14];
+  Mb[2] += t.V * Gb[1] + t.v2 * Gb[6] + VW * Gb[7] + h * t.vr * Gb[8];
+  Mb[3] += h * t.V * Gb[4] + t.V * Gb[5] + h * t.v2 * Gb[11] + h * VW * Gb[13] + h * t.vr * Gb[14];
+  Mb[4] += h * t.V * Gb[8];
+  Mb[5] += q * t.V * Gb[14];
+  tb.V += M[1] * Gb[0] + M[2] * Gb[1] + t.W * M[1] * Gb[3] + h * M[3] * Gb[4] + M[3] * Gb[5] + t.W * M[2] * Gb[7] +
+          h * M[4] * Gb[8] + t.w2 * M[1] * Gb[12] + h * t.W * M[3] * Gb[13] + q * M[5] * Gb[14];
+  tb.W += t.V * M[1] * Gb[3] + t.V * M[2] * Gb[7] + t.v2 * M[1] * Gb[10] + h * t.V * M[3] * Gb[13];
+  tb.v2 += M[1] * Gb[2] + M[2] * Gb[6] + t.W * M[1] * Gb[10] + h * M[3] * Gb[11];
+  tb.vr += h * (M[1] * Gb[4] + M[2] * Gb[8] + M[3] * Gb[14]);
+  tb.v3 += M[1] * Gb[9];
+  tb.v2r += h * M[1] * Gb[11];
+  tb.w2 += t.V * M[1] * Gb[12];
+  tb.vwr += h * M[1] * Gb[13];
+  tb.vr2 += q * M[1] * Gb[14];
+}
+
+template <class T>
+DGK_HD void mat_Gw_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb, TransverseBar<T>& tb) {
+  const T h = T(0.5), q = T(0.25), VW = t.V * t.W;
+  Mb[1] += t.W * Gb[0] + VW * Gb[2] + t.w2 * Gb[3] + h * t.wr * Gb[4] + t.W * t.v2 * Gb[9] + t.V * t.w2 * Gb[10] +
+           h * t.vwr * Gb[11] + t.w3 * Gb[12] + h * t.w2r * Gb[13] + q * t.wr2 * Gb[14];
+  Mb[2] += t.W * Gb[1] + VW * Gb[6] + t.w2 * Gb[7] + h * t.wr * Gb[8];
+  Mb[3] += h * t.W * Gb[4] + t.W * Gb[5] + h * VW * Gb[11] + h * t.w2 * Gb[13] + h * t.wr * Gb[14];
+  Mb[4] += h * t.W * Gb[8];
+  Mb[5] += q * t.W * Gb[14];
+  tb.W += M[1] * Gb[0] + M[2] * Gb[1] + t.V * M[1] * Gb[2] + h * M[3] * Gb[4] + M[3] * Gb[5] + t.V * M[2] * Gb[6] +
+          h * M[4] * Gb[8] + t.v2 * M[1] * Gb[9] + h * t.V * M[3] * Gb[11] + q * M[5] * Gb[14];
+  tb.V += t.W * M[1] * Gb[2] + t.W * M[2] * Gb[6] + t.w2 * M[1] * Gb[10] + h * t.W * M[3] * Gb[11];
+  tb.w2 += M[1] * Gb[3] + M[2] * Gb[7] + t.V * M[1] * Gb[10] + h * M[3] * Gb[13];
+  tb.wr += h * (M[1] * Gb[4] + M[2] * Gb[8] + M[3] * Gb[14]);
+  tb.v2 += t.W * M[1] * Gb[9];
+  tb.vwr += h * M[1] * Gb[11];
+  tb.w3 += M[1] * Gb[12];
+  tb.w2r += h * M[1] * Gb[13];
+  tb.wr2 += q * M[1] * Gb[14];
+}
+
+// Reverse of y += r S x (S symmetric, upper triangle in row order): adds the
+// cotangents of S, x and r.  With z = S ybar: xbar += r z, rbar += x.z,
+// Sbar_kj += r (ybar_k x_j + ybar_j x_k) (k < j), Sbar_kk += r ybar_k x_k.
+template <class T>
+DGK_HD void sym_mv_bwd(const T S[15], const T x[5], T r, const T yb[5], T Sb[15], T xb[5], T& rb) {
+  T z[5];
+  z[0] = S[0] * yb[0] + S[1] * yb[1] + S[2] * yb[2] + S[3] * yb[3] + S[4] * yb[4];
+  z[1] = S[1] * yb[0] + S[5] * yb[1] + S[6] * yb[2] + S[7] * yb[3] + S[8] * yb[4];
+  z[2] = S[2] * yb[0] + S[6] * yb[1] + S[9] * yb[2] + S[10] * yb[3] + S[11] * yb[4];
+  z[3] = S[3] * yb[0] + S[7] * yb[1] + S[10] * yb[2] + S[12] * yb[3] + S[13] * yb[4];
+  z[4] = S[4] * yb[0] + S[8] * yb[1] + S[11] * yb[2] + S[13] * yb[3] + S[14] * yb[4];
+  T d = T(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    xb[k] += r * z[k];
+    d += x[k] * z[k];
+  }
+  rb += d;
+  T u[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) u[k] = r * yb[k];
+  int i = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int j = k; j < 5; ++j, ++i) Sb[i] += (j == k) ? u[k] * x[k] : u[k] * x[j] + u[j] * x[k];
+}
+
+// Reverse of face_side (moment-matrix form).  Adds the cotangents of the
+// side's trace (q, dq) given those of its accumulator contributions.
 template <int SIDE, class T>
 DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const FaceAcc<T>& accb, T qb[5],
-                          T dqb[3][5]) {
+                              T dqb[3][5]) {
   const T K = T(ph.K), gm1 = T(ph.gm1), inv_k3 = T(ph.inv_k3);
   const Prim<T> s = primitive(q, gm1);
   const Solver5<T> S(s, K, inv_k3);
@@ -498,78 +596,65 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
 #pragma unroll
   for (int k = 0; k < 5; ++k) bA[k] = dtq[k] * ir;
   S(bA, A);
-  Mom<T> h;
-  mom_half(s.U, s.th, SIDE, h.u);
-  mom_full(s.V, s.th, h.v);
-  mom_full(s.W, s.th, h.w);
-  mom_xi(K, s.th, h);
+  T M[7];
+  mom_half(s.U, s.th, SIDE, M);
+  const Transverse<T> tr(s.V, s.W, s.th, K);
   const T r = s.rho;
 
-  Prim<T> sb = prim_zero<T>();
-  Mom<T> hb;
-  mom_zero(hb);
+  T Mb[7];
+#pragma unroll
+  for (int n = 0; n < 7; ++n) Mb[n] = T(0);
+  TransverseBar<T> trb = transverse_bar_zero<T>();
   T ab[3][5], Ab[5];
 #pragma unroll
   for (int i = 0; i < 3; ++i) zero5(ab[i]);
   zero5(Ab);
-  T y[5], g[5];
   T rb = T(0);
-  // Q0 += r psim<0,0,0>(h)
-  psim<0, 0, 0>(h, y);
+  T H[15], Hb[15];
+  // <psi psi^T>: Q0 (its first column) and dQ0_i
+  mat_H<0>(M, tr, H);
+#pragma unroll
+  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    rb += accb.Q0[k] * y[k];
-    g[k] = r * accb.Q0[k];
+    rb += accb.Q0[k] * H[k];
+    Hb[k] += r * accb.Q0[k];
   }
-  psim_bwd<0, 0, 0>(h, g, hb);
-  // dQ0[i] += r Gpsi<0,0,0>(h, a_i)
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    Gpsi<0, 0, 0>(h, a[i], y);
+  for (int i = 0; i < 3; ++i) sym_mv_bwd(H, a[i], r, accb.dQ0[i], Hb, ab[i], rb);
+  mat_H_bwd<0>(M, tr, Hb, Mb, trb);
+  // <u psi psi^T>: m4 (first column) and m6
+  mat_H<1>(M, tr, H);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      rb += accb.dQ0[i][k] * y[k];
-      g[k] = r * accb.dQ0[i][k];
-    }
-    Gpsi_bwd<0, 0, 0>(h, a[i], g, hb, ab[i]);
-  }
-  // m4 += r psim<1,0,0>(h)
-  psim<1, 0, 0>(h, y);
+  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    rb += accb.m4[k] * y[k];
-    g[k] = r * accb.m4[k];
+    rb += accb.m4[k] * H[k];
+    Hb[k] += r * accb.m4[k];
   }
-  psim_bwd<1, 0, 0>(h, g, hb);
-  // m5 += r (Gpsi<2,0,0>(h,a0) + Gpsi<1,1,0>(h,a1) + Gpsi<1,0,1>(h,a2))
-  {
-    T z0[5], z1[5], z2[5];
-    Gpsi<2, 0, 0>(h, a[0], z0);
-    Gpsi<1, 1, 0>(h, a[1], z1);
-    Gpsi<1, 0, 1>(h, a[2], z2);
+  sym_mv_bwd(H, A, r, accb.m6, Hb, Ab, rb);
+  mat_H_bwd<1>(M, tr, Hb, Mb, trb);
+  // m5 = r (<u^2 psi psi^T> a_0 + <u v psi psi^T> a_1 + <u w psi psi^T> a_2)
+  mat_H<2>(M, tr, H);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      rb += accb.m5[k] * (z0[k] + z1[k] + z2[k]);
-      g[k] = r * accb.m5[k];
-    }
-    Gpsi_bwd<2, 0, 0>(h, a[0], g, hb, ab[0]);
-    Gpsi_bwd<1, 1, 0>(h, a[1], g, hb, ab[1]);
-    Gpsi_bwd<1, 0, 1>(h, a[2], g, hb, ab[2]);
-  }
-  // m6 += r Gpsi<1,0,0>(h, A)
-  Gpsi<1, 0, 0>(h, A, y);
+  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
+  sym_mv_bwd(H, a[0], r, accb.m5, Hb, ab[0], rb);
+  mat_H_bwd<2>(M, tr, Hb, Mb, trb);
+  mat_Gv(M, tr, H);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    rb += accb.m6[k] * y[k];
-    g[k] = r * accb.m6[k];
-  }
-  Gpsi_bwd<1, 0, 0>(h, A, g, hb, Ab);
+  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
+  sym_mv_bwd(H, a[1], r, accb.m5, Hb, ab[1], rb);
+  mat_Gv_bwd(M, tr, Hb, Mb, trb);
+  mat_Gw(M, tr, H);
+#pragma unroll
+  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
+  sym_mv_bwd(H, a[2], r, accb.m5, Hb, ab[2], rb);
+  mat_Gw_bwd(M, tr, Hb, Mb, trb);
+
+  Prim<T> sb = prim_zero<T>();
   sb.rho += rb;
-  // moment tables
-  mom_half_bwd(s.U, s.th, SIDE, h.u, hb.u, sb.U, sb.th);
-  mom_full_bwd(s.V, s.th, h.v, hb.v, sb.V, sb.th);
-  mom_full_bwd(s.W, s.th, h.w, hb.w, sb.W, sb.th);
-  mom_xi_bwd(K, s.th, hb, sb.th);
+  transverse_bwd(tr, s.th, K, trb, sb.V, sb.W, sb.th);
+  mom_half_bwd(s.U, s.th, SIDE, M, Mb, sb.U, sb.th);
   // time slope A = S(dt/rho), dt = -sum_e J_e dq_e
   Solver5Bar<T> Sb;
   T bAb[5], dtqb[5];

@@ -49,34 +49,6 @@ struct AdjIn {
   }
 };
 
-// Trace basis of a face with normal axis D: for side s (0: xi_D = +1, 1: -1)
-// and face point qf = b NQ + a (tangential axes D+1, D+2):
-// value, and reference derivatives along (D, D+1, D+2).
-template <class T, int K, int NQ, int D>
-struct TraceTab {
-  static constexpr int NM = nmodes(K), NQ2 = NQ * NQ;
-  T B[2][NM][NQ2], Dn[2][NM][NQ2], D1[2][NM][NQ2], D2[2][NM][NQ2];
-  constexpr TraceTab() : B{}, Dn{}, D1{}, D2{} {
-    constexpr Modes<K> md{};
-    for (int s = 0; s < 2; ++s)
-      for (int n = 0; n < NM; ++n)
-        for (int b = 0; b < NQ; ++b)
-          for (int a = 0; a < NQ; ++a) {
-            const int ed = md.e[n][D], e1 = md.e[n][(D + 1) % 3], e2 = md.e[n][(D + 2) % 3];
-            const double xd = s == 0 ? 1.0 : -1.0, xa = Gauss<NQ>::x[a], xb = Gauss<NQ>::x[b];
-            const int qf = b * NQ + a;
-            B[s][n][qf] = T(leg(ed, xd) * leg(e1, xa) * leg(e2, xb));
-            Dn[s][n][qf] = T(dleg(ed, xd) * leg(e1, xa) * leg(e2, xb));
-            D1[s][n][qf] = T(leg(ed, xd) * dleg(e1, xa) * leg(e2, xb));
-            D2[s][n][qf] = T(leg(ed, xd) * leg(e1, xa) * dleg(e2, xb));
-          }
-  }
-};
-template <class T, int K, int NQ, int D>
-struct TraceTabHolder {
-  static constexpr TraceTab<T, K, NQ, D> t{};
-};
-
 // Volume basis values and reference gradients at the volume points.
 template <class T, int K, int NQ>
 struct VolBasis {

@@ -10,10 +10,10 @@
 //                 contiguous row, the rows of a tile at fixed offsets.
 //
 // One stage is two launches:
-//   face_kernel   -- every face of the grid once: traces of both cells at the
-//                    face Gauss points (coefficients staged through LDS), the
-//                    gas-kinetic face flux per point, then the projection on
-//                    the tangential modes.  One lane per face point.
+//   face_kernel   -- one lane per face, every face of the grid once: traces
+//                    of both cells at the face Gauss points, the gas-kinetic
+//                    face flux per point, and its projection on the
+//                    tangential modes of the face.
 //   volume_kernel -- one lane per cell: point values and gradients at the
 //                    volume Gauss points, the volume flux per point, the
 //                    projection sum_q w_q F_d dB_n/dx_d in registers, the
@@ -143,10 +143,36 @@ struct FaceTabHolder {
   static constexpr FaceTab<T, K, NQ> t{};
 };
 
-// --------------------------------------------------------------------------
-// Face kernel.  Block = 4 wavefronts; each wavefront takes FPW = 64/NQ^2
-// faces, one lane per face point.  gridDim.y = face normal direction.
-// --------------------------------------------------------------------------
+// Trace basis of a face with normal axis D: for side s (0: xi_D = +1, 1: -1)
+// and face point qf = b NQ + a (tangential axes D+1, D+2):
+// value, and reference derivatives along (D, D+1, D+2).
+template <class T, int K, int NQ, int D>
+struct TraceTab {
+  static constexpr int NM = nmodes(K), NQ2 = NQ * NQ;
+  T B[2][NM][NQ2], Dn[2][NM][NQ2], D1[2][NM][NQ2], D2[2][NM][NQ2];
+  constexpr TraceTab() : B{}, Dn{}, D1{}, D2{} {
+    constexpr Modes<K> md{};
+    for (int s = 0; s < 2; ++s)
+      for (int n = 0; n < NM; ++n)
+        for (int b = 0; b < NQ; ++b)
+          for (int a = 0; a < NQ; ++a) {
+            const int ed = md.e[n][D], e1 = md.e[n][(D + 1) % 3], e2 = md.e[n][(D + 2) % 3];
+            const double xd = s == 0 ? 1.0 : -1.0, xa = Gauss<NQ>::x[a], xb = Gauss<NQ>::x[b];
+            const int qf = b * NQ + a;
+            B[s][n][qf] = T(leg(ed, xd) * leg(e1, xa) * leg(e2, xb));
+            Dn[s][n][qf] = T(dleg(ed, xd) * leg(e1, xa) * leg(e2, xb));
+            D1[s][n][qf] = T(leg(ed, xd) * dleg(e1, xa) * leg(e2, xb));
+            D2[s][n][qf] = T(leg(ed, xd) * leg(e1, xa) * dleg(e2, xb));
+          }
+  }
+};
+template <class T, int K, int NQ, int D>
+struct TraceTabHolder {
+  static constexpr TraceTab<T, K, NQ, D> t{};
+};
+
+// Blocking of the adjoint face kernel: FPW = 64/NQ^2 faces per wavefront,
+// one lane per face point, 4 wavefronts per block.
 template <int K, int NQ>
 struct FaceCfg {
   static constexpr int NM = nmodes(K), NT = ntan(K), NQ2 = NQ * NQ;
@@ -154,126 +180,109 @@ struct FaceCfg {
   static constexpr int CS = 5 * NM + 1;  // LDS stride of one cell's coefficients
 };
 
+// Cell-per-lane kernels: 4 wavefronts per block.
+constexpr int kCellThreads = 256;
+
+// Block order for the 8 XCDs: the hardware hands consecutive block indices to
+// the XCDs in turn; this bijection of [0, nb) gives XCD x (= b mod 8) one
+// contiguous range of logical blocks, so that neighbouring cells (and the face
+// records they share) stay in one XCD's L2.
+DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b & 7u, q = nb >> 3, r = nb & 7u;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// --------------------------------------------------------------------------
+// Face kernel.  One lane per face: the face between cell f (lower side) and
+// its upper neighbour along D, 64 faces (one tile of lower cells) per
+// wavefront.  The lane keeps the coefficients of both cells in registers and
+// visits the face points in a loop that is uniform across the wavefront
+// (trace basis and projection weights by scalar loads); per point the traces
+// of both sides, the gas-kinetic face flux, and its projection on the
+// tangential modes accumulated in registers.  Each record component is then
+// stored as one row of the tile.
+// --------------------------------------------------------------------------
 template <class T, int K, int NQ, bool NEED_F, int D>
-DGK_D void face_block(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
-                      long long f0, T (*sq)[FaceCfg<K, NQ>::FPB][FaceCfg<K, NQ>::CS],
-                      T (*sF)[FaceCfg<K, NQ>::NQ2][10]) {
-  using C = FaceCfg<K, NQ>;
-  constexpr int NM = C::NM, NT = C::NT, NQ2 = C::NQ2, FPW = C::FPW, FPB = C::FPB;
+DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
+                     long long f) {
+  constexpr int NM = nmodes(K), NT = ntan(K), NQ2 = NQ * NQ;
   constexpr int NF = NEED_F ? 2 : 1;
   constexpr int RECN = 5 * NF * NT;
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const int tid = threadIdx.x;
+  constexpr Modes<K> md{};
+  // local frame: velocity (normal, t1, t2) = global (D, T1, T2)
+  constexpr int vmap[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};
+  using TT = TraceTabHolder<T, K, NQ, D>;
+  using FT = FaceTabHolder<T, K, NQ>;
   const long long N = g.ncell;
+  const bool act = f < N;
+  const long long fl = act ? f : N - 1;  // lanes past the end recompute the last face, store nothing
+  const long long fu = (long long)nb32(unsigned(fl), D, +1, g);
 
-  // upper neighbours of the block's faces, then the coefficients of the lower
-  // (side 0) and upper (side 1) cells
-  __shared__ unsigned snb[FPB];
-  if (tid < FPB && f0 + tid < N) snb[tid] = nb32(unsigned(f0 + tid), D, +1, g);
-  __syncthreads();
-  for (int idx = tid; idx < 2 * FPB * 5 * NM; idx += 256) {
-    const int side = idx / (FPB * 5 * NM);
-    const int r = idx - side * (FPB * 5 * NM);
-    const int vm = r / FPB, j = r - vm * FPB;
-    const long long f = f0 + j;
-    if (f < N) {
-      const long long c = side ? (long long)snb[j] : f;
-      sq[side][j][vm] = q[(long long)vm * N + c];
-    }
-  }
-  __syncthreads();
-
-  const int w = tid >> 6, l = tid & 63;
-  const int fl = w * FPW + l / NQ2, qp = l % NQ2;
-  const bool active = (l < FPW * NQ2) && (f0 + fl < N);
-  if (active) {
-    const int qa = qp % NQ, qb = qp / NQ;
-    const double xa = gauss_x<NQ>(qa), xb = gauss_x<NQ>(qb);
-    T Pa[K + 1], dPa[K + 1], Pb[K + 1], dPb[K + 1];
+  T cf[2][5][NM];
 #pragma unroll
-    for (int i = 0; i <= K; ++i) {
-      Pa[i] = T(leg(i, xa));
-      dPa[i] = T(dleg(i, xa));
-      Pb[i] = T(leg(i, xb));
-      dPb[i] = T(dleg(i, xb));
-    }
-    const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
-    // local frame: velocity (normal, t1, t2) = global (D, T1, T2)
-    constexpr int vmap[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};
-    // trace of one side at the point: Q and its derivatives along (n, t1, t2)
-    auto trace = [&](auto side_c, T qs[5], T dqs[3][5]) {
-      constexpr int side = decltype(side_c)::value;
+  for (int vm = 0; vm < 5 * NM; ++vm) {
+    cf[0][vm / NM][vm % NM] = q[(long long)vm * N + fl];
+    cf[1][vm / NM][vm % NM] = q[(long long)vm * N + fu];
+  }
+  T acc[5 * NF][NT];
+#pragma unroll
+  for (int r = 0; r < 5 * NF; ++r)
+#pragma unroll
+    for (int m = 0; m < NT; ++m) acc[r][m] = T(0);
+  const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
+  int bad = 0;
+#pragma unroll 1
+  for (int qf = 0; qf < NQ2; ++qf) {
+    FaceAcc<T> fa;
+    face_acc_zero(fa);
+    static_for<2>([&](auto sc) {
+      constexpr int side = decltype(sc)::value;
+      // trace of this side at the point: Q and its derivatives along (n, t1, t2)
+      T qs[5], dqs[3][5];
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
-        const T* c = &sq[side][fl][vmap[vl] * NM];
         T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0);
         static_for<NM>([&](auto nc) {
           constexpr int n = decltype(nc)::value;
-          constexpr Modes<K> md{};
-          constexpr int ed = md.e[n][D], e1 = md.e[n][T1], e2 = md.e[n][T2];
-          // P_ed(+1) = 1, P_ed(-1) = (-1)^ed; P'_ed(+1) = ed(ed+1)/2, P'_ed(-1) = (-1)^(ed+1) ed(ed+1)/2
-          constexpr double pv = (side == 0) ? 1.0 : ((ed % 2) ? -1.0 : 1.0);
-          constexpr double dv = ((side == 0) ? 1.0 : ((ed % 2) ? 1.0 : -1.0)) * 0.5 * ed * (ed + 1);
-          const T cn = c[n];
-          const T t12 = Pa[e1] * Pb[e2];
-          v0 += cn * (T(pv) * t12);
-          if constexpr (ed > 0) vn += cn * (T(dv) * t12);
-          if constexpr (e1 > 0) v1 += cn * (T(pv) * dPa[e1] * Pb[e2]);
-          if constexpr (e2 > 0) v2 += cn * (T(pv) * Pa[e1] * dPb[e2]);
+          const T c = cf[side][vmap[vl]][n];
+          v0 += c * TT::t.B[side][n][qf];
+          if constexpr (md.e[n][D] > 0) vn += c * TT::t.Dn[side][n][qf];
+          if constexpr (md.e[n][T1] > 0) v1 += c * TT::t.D1[side][n][qf];
+          if constexpr (md.e[n][T2] > 0) v2 += c * TT::t.D2[side][n][qf];
         });
         qs[vl] = v0;
         dqs[0][vl] = vn * sn;
         dqs[1][vl] = v1 * s1;
         dqs[2][vl] = v2 * s2;
       }
-    };
+      face_side<side == 0 ? +1 : -1>(ph, qs, dqs, fa, bad);
+    });
     T F[5], Ft[5];
-    int bad = 0;
-    FaceAcc<T> acc;
-    face_acc_zero(acc);
-    {
-      T qs[5], dqs[3][5];
-      trace(std::integral_constant<int, 0>{}, qs, dqs);
-      face_side<+1>(ph, qs, dqs, acc, bad);
-    }
-    {
-      T qs[5], dqs[3][5];
-      trace(std::integral_constant<int, 1>{}, qs, dqs);
-      face_side<-1>(ph, qs, dqs, acc, bad);
-    }
-    face_finish<T, NEED_F>(ph, acc, F, Ft, bad);
-    if (bad) atomicOr(flag, 1);
-    // back to global variable order
+    face_finish<T, NEED_F>(ph, fa, F, Ft, bad);
+    // record component order: (F|Ft, global variable, tangential mode)
+    static_for<NT>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      const T p = FT::t.phi[m][qf];
 #pragma unroll
-    for (int vl = 0; vl < 5; ++vl) {
-      if constexpr (NEED_F) {
-        sF[fl][qp][vmap[vl]] = F[vl];
-        sF[fl][qp][5 + vmap[vl]] = Ft[vl];
-      } else {
-        sF[fl][qp][vmap[vl]] = Ft[vl];
+      for (int vl = 0; vl < 5; ++vl) {
+        if constexpr (NEED_F) acc[vmap[vl]][m] += p * F[vl];
+        acc[(NF - 1) * 5 + vmap[vl]][m] += p * Ft[vl];
       }
-    }
+    });
   }
-  __syncthreads();
-  // projection on the tangential modes: rec = sum_qf phi[m][qf] F(qf); the
-  // block's faces run fastest so that each record row is written contiguously
-  const auto& ft = FaceTabHolder<T, K, NQ>::t;
-  for (int o = tid; o < FPB * RECN; o += 256) {
-    const int fo = o % FPB, r = o / FPB;
-    const int comp = r / NT, m = r - comp * NT;  // comp = F|Ft * 5 + var  (NF = 2) or var
-    const long long f = f0 + fo;
-    if (f < N) {
-      T s = T(0);
+  if (!act) return;
+  if (bad) atomicOr(flag, 1);
+  T* out = rec + rec_index(D, f, 0, RECN, (N + 63) >> 6);
 #pragma unroll
-      for (int k = 0; k < NQ2; ++k) s += ft.phi[m][k] * sF[fo][k][comp];
-      rec[rec_index(D, f, r, RECN, (N + 63) >> 6)] = s;
-    }
-  }
+  for (int r = 0; r < 5 * NF; ++r)
+#pragma unroll
+    for (int m = 0; m < NT; ++m) out[(r * NT + m) * 64] = acc[r][m];
 }
 
 // Minimum waves per SIMD requested for the face kernel (register budget).
 #ifndef DGK_FACE_WAVES_F32
-#define DGK_FACE_WAVES_F32 3
+#define DGK_FACE_WAVES_F32 1
 #endif
 #ifndef DGK_FACE_WAVES_F64
 #define DGK_FACE_WAVES_F64 1
@@ -283,17 +292,21 @@ struct FaceWaves {
   static constexpr int value = sizeof(T) == 4 ? DGK_FACE_WAVES_F32 : DGK_FACE_WAVES_F64;
 };
 
+// Grid: 3 nb blocks of kCellThreads lanes, nb = ceil(N / kCellThreads); the
+// logical block (after the XCD reordering) picks the normal axis and the
+// range of faces.
 template <class T, int K, int NQ, bool NEED_F>
-__global__ __launch_bounds__(256, FaceWaves<T>::value) void face_kernel(const T* __restrict__ q, T* __restrict__ rec, Geo g, Phys ph,
-                                                   int* flag) {
-  using C = FaceCfg<K, NQ>;
-  __shared__ T sq[2][C::FPB][C::CS];
-  __shared__ T sF[C::FPB][C::NQ2][10];
-  const long long f0 = (long long)blockIdx.x * C::FPB;
-  switch (blockIdx.y) {
-    case 0: face_block<T, K, NQ, NEED_F, 0>(q, rec, g, ph, flag, f0, sq, sF); break;
-    case 1: face_block<T, K, NQ, NEED_F, 1>(q, rec, g, ph, flag, f0, sq, sF); break;
-    default: face_block<T, K, NQ, NEED_F, 2>(q, rec, g, ph, flag, f0, sq, sF); break;
+__global__ __launch_bounds__(kCellThreads, FaceWaves<T>::value) void face_kernel(const T* __restrict__ q,
+                                                                                T* __restrict__ rec, Geo g,
+                                                                                Phys ph, int* flag) {
+  const unsigned nb = gridDim.x / 3;
+  const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned d = lb / nb;
+  const long long f = (long long)(lb - d * nb) * kCellThreads + threadIdx.x;
+  switch (d) {
+    case 0: face_lane<T, K, NQ, NEED_F, 0>(q, rec, g, ph, flag, f); break;
+    case 1: face_lane<T, K, NQ, NEED_F, 1>(q, rec, g, ph, flag, f); break;
+    default: face_lane<T, K, NQ, NEED_F, 2>(q, rec, g, ph, flag, f); break;
   }
 }
 
@@ -332,10 +345,9 @@ struct VolCfg {
   static constexpr int CS = 5 * NM + 1;
 };
 
-// Cell-per-lane kernels: 4 wavefronts per block; minimum waves per SIMD
-// requested from the register allocator (FP32: two resident wavefronts per
-// SIMD hide the memory phases; FP64 needs twice the registers).
-constexpr int kCellThreads = 256;
+// Minimum waves per SIMD requested from the register allocator for the
+// volume kernel (FP32: two resident wavefronts per SIMD hide the memory
+// phases; FP64 needs twice the registers).
 template <class T>
 struct CellWaves {
   static constexpr int value = sizeof(T) == 4 ? 2 : 1;
@@ -371,15 +383,6 @@ template <class T, int K, int NQ>
 struct PointBasisHolder {
   static constexpr PointBasis<T, K, NQ> t{};
 };
-
-// Block order for the 8 XCDs: the hardware hands consecutive block indices to
-// the XCDs in turn; this bijection of [0, nb) gives XCD x (= b mod 8) one
-// contiguous range of logical blocks, so that neighbouring cells (and the face
-// records they share) stay in one XCD's L2.
-DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
-  const unsigned x = b & 7u, q = nb >> 3, r = nb & 7u;
-  return x * q + (x < r ? x : r) + (b >> 3);
-}
 
 template <class T, int K, int NQ, int MODE>
 __global__ __launch_bounds__(kCellThreads, CellWaves<T>::value) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,

@@ -30,16 +30,14 @@ int launch_convert(dg_hgks_ctx* c, const double* a, T* b, long long n) {
 // One operator evaluation (face pass + volume pass).
 template <class T, int K, int NQ, int MODE>
 int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g, const Phys& ph) {
-  using FC = FaceCfg<K, NQ>;
   T* rec = (T*)(c->ws + c->lay.rec);
   int* flag = (int*)(c->ws + c->lay.flag);
   const long long N = g.ncell;
-  const unsigned bpd = (unsigned)((N + FC::FPB - 1) / FC::FPB);
   const unsigned nvb = (unsigned)((N + kCellThreads - 1) / kCellThreads);
   if constexpr (MODE == 1) {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, rec, g, ph, flag)));
+    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(3 * nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, flag)));
   } else {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, rec, g, ph, flag)));
+    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(3 * nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, flag)));
   }
   DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE><<<dim3(nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, o, flag)));
   return DG_HGKS_OK;

@@ -27,7 +27,8 @@ import numpy as np  # noqa: E402
 # volume point of each stage, for the kernels' own formulas.
 FLOPS_JSON = os.path.join(ROOT, "paper_2202_13821_amd", "flops.json")
 
-MI355X_PEAK = {"fp32_vector": 157.3, "fp64_vector": 78.6, "hbm_GBs": 8000.0}
+# published peaks; the non-packed FP32 rate is what code without v_pk_*_f32 can reach
+MI355X_PEAK = {"fp32_vector": 157.3, "fp32_vector_nonpacked": 78.6, "fp64_vector": 78.6, "hbm_GBs": 8000.0}
 
 
 def parse():
@@ -79,9 +80,9 @@ def time_path(precision, n, steps, warmup, timing=True):
 
 
 def adjoint_ratio(precision, n=32, nsteps=200, stride=15):
-    """adj/fwd on the P2 Taylor-Green 32^3 adjoint configuration: wall time of
-    the gradient call (segment recomputation + reverse sweep) over that of the
-    checkpointing forward call."""
+    """adj/fwd on a P2 Taylor-Green run (default: the 32^3, 200-step adjoint
+    configuration): wall time of the gradient call (segment recomputation +
+    reverse sweep) over that of the checkpointing forward call."""
     import torch
 
     from paper_2202_13821_amd import Solver, kinetic_energy, problems
@@ -190,6 +191,7 @@ def main():
                       "cells": n ** 3, "modes": 10, "dof_per_step": dof}}
     sec32, k32, q32, s32 = time_path("fp32_bulk", n, a.steps, a.warmup)
     out["value"] = dof / sec32
+    out["dof_updates_per_variable_per_s"] = dof / 5 / sec32
     out["ms_per_step"] = 1e3 * sec32
     out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else None) for k, v in k32.items()}
     flops = load_flops()
@@ -204,6 +206,7 @@ def main():
         out["roofline"] = {"bound": "alu", "kernel": "face_kernel<float,2,3> (both stages, averaged per launch)",
                            "achieved": achieved, "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
                            "frac": achieved / MI355X_PEAK["fp32_vector"],
+                           "frac_nonpacked": achieved / MI355X_PEAK["fp32_vector_nonpacked"],
                            "traffic": measured_traffic("face_kernel<float,2,3>"),
                            "flops_per_launch": w, "avg_launch_ms": face_ms,
                            "flops_per_point": 0.5 * (flops["fp32"]["face_stage1"] + flops["fp32"]["face_stage2"])}
@@ -211,6 +214,7 @@ def main():
         out["roofline_volume"] = {"bound": "alu", "achieved": wv / (vol_ms * 1e-3) / 1e12,
                                   "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
                                   "frac": wv / (vol_ms * 1e-3) / 1e12 / MI355X_PEAK["fp32_vector"],
+                                  "frac_nonpacked": wv / (vol_ms * 1e-3) / 1e12 / MI355X_PEAK["fp32_vector_nonpacked"],
                                   "traffic": measured_traffic("volume_kernel<float,2,3>")}
         per_step = flops["per_step_per_cell"]["fp32"] * n ** 3
         out["step_flops"] = per_step
@@ -220,6 +224,13 @@ def main():
         sec64, k64, q64, s64 = time_path("fp64", n, a.steps, a.warmup)
         out["fp64"] = {"value": dof / sec64, "ms_per_step": 1e3 * sec64,
                        "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in k64.items()}}
+        if flops:
+            f64_ms = k64["face"][0] / max(k64["face"][1], 1)
+            w64 = 0.5 * (flops["fp64"]["face_stage1"] + flops["fp64"]["face_stage2"]) * 3 * n ** 3 * 9
+            out["fp64"]["roofline"] = {"bound": "alu", "kernel": "face_kernel<double,2,3>",
+                                       "achieved": w64 / (f64_ms * 1e-3) / 1e12, "peak": MI355X_PEAK["fp64_vector"],
+                                       "unit": "TFLOP/s",
+                                       "frac": w64 / (f64_ms * 1e-3) / 1e12 / MI355X_PEAK["fp64_vector"]}
         out["speedup_fp32_bulk_vs_fp64"] = sec64 / sec32
         d = (q32 - q64).reshape(5, -1)
         r = q64.reshape(5, -1)
@@ -228,7 +239,8 @@ def main():
             float(torch.linalg.norm(d[list(g)]) / torch.linalg.norm(r[list(g)])) for g in groups)
         del s64
     if not a.no_adjoint:
-        out["adjoint"] = {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64")}
+        out["adjoint"] = {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64"),
+                          "fp32_bulk_128": adjoint_ratio("fp32_bulk", n=n, nsteps=6, stride=3)}
         out["adj_over_fwd"] = out["adjoint"]["fp32_bulk"]["adj_over_fwd"]
     if a.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)

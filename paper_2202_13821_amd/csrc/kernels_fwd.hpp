@@ -143,6 +143,29 @@ struct FaceTabHolder {
   static constexpr FaceTab<T, K, NQ> t{};
 };
 
+// Unweighted tangential basis and its reference derivatives at the face
+// points: val[qf][m] = P_ma(x_a) P_mb(x_b), d1 = P'_ma P_mb, d2 = P_ma P'_mb.
+template <class T, int K, int NQ>
+struct TanBasis {
+  static constexpr int NT = ntan(K);
+  T val[NQ * NQ][NT], d1[NQ * NQ][NT], d2[NQ * NQ][NT];
+  constexpr TanBasis() : val{}, d1{}, d2{} {
+    constexpr TanModes<K> tm{};
+    for (int b = 0; b < NQ; ++b)
+      for (int a = 0; a < NQ; ++a)
+        for (int m = 0; m < NT; ++m) {
+          const double xa = Gauss<NQ>::x[a], xb = Gauss<NQ>::x[b];
+          val[b * NQ + a][m] = T(leg(tm.e[m][0], xa) * leg(tm.e[m][1], xb));
+          d1[b * NQ + a][m] = T(dleg(tm.e[m][0], xa) * leg(tm.e[m][1], xb));
+          d2[b * NQ + a][m] = T(leg(tm.e[m][0], xa) * dleg(tm.e[m][1], xb));
+        }
+  }
+};
+template <class T, int K, int NQ>
+struct TanBasisHolder {
+  static constexpr TanBasis<T, K, NQ> t{};
+};
+
 // Trace basis of a face with normal axis D: for side s (0: xi_D = +1, 1: -1)
 // and face point qf = b NQ + a (tangential axes D+1, D+2):
 // value, and reference derivatives along (D, D+1, D+2).
@@ -205,32 +228,58 @@ DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
 template <class T, int K, int NQ, bool NEED_F, int D>
 DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
                      long long f) {
-  constexpr int NM = nmodes(K), NT = ntan(K), NQ2 = NQ * NQ;
+  constexpr int NM = nmodes(K), NT = ntan(K), NT1 = ntan(K - 1), NQ2 = NQ * NQ;
   constexpr int NF = NEED_F ? 2 : 1;
   constexpr int RECN = 5 * NF * NT;
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   constexpr Modes<K> md{};
   // local frame: velocity (normal, t1, t2) = global (D, T1, T2)
   constexpr int vmap[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};
-  using TT = TraceTabHolder<T, K, NQ, D>;
   using FT = FaceTabHolder<T, K, NQ>;
   const long long N = g.ncell;
   const bool act = f < N;
   const long long fl = act ? f : N - 1;  // lanes past the end recompute the last face, store nothing
   const long long fu = (long long)nb32(unsigned(fl), D, +1, g);
 
-  T cf[2][5][NM];
+  // The traces on this face depend on a cell's modes only through their
+  // values at xi_D = +-1: per side s and variable, the tangential-mode
+  // coefficients of the trace, ct[s][v][t] = sum_{e_D} c[v][n(e_D, t)] P_{e_D}(+-1),
+  // and of its normal derivative, cn[s][v][t] = sum_{e_D} c[v][n] P'_{e_D}(+-1)
+  // (tangential degree <= K - 1), with P_e(+1) = 1, P_e(-1) = (-1)^e,
+  // P'_e(+1) = e(e+1)/2, P'_e(-1) = (-1)^(e+1) e(e+1)/2.
+  T ct[2][5][NT], cn[2][5][NT1];
 #pragma unroll
-  for (int vm = 0; vm < 5 * NM; ++vm) {
-    cf[0][vm / NM][vm % NM] = q[(long long)vm * N + fl];
-    cf[1][vm / NM][vm % NM] = q[(long long)vm * N + fu];
-  }
+  for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) ct[sd][v][t] = T(0);
+#pragma unroll
+      for (int t = 0; t < NT1; ++t) cn[sd][v][t] = T(0);
+    }
+  static_for<2>([&](auto sc) {
+    constexpr int side = decltype(sc)::value;
+    const long long cell = side ? fu : fl;
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      static_for<NM>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        constexpr int ed = md.e[n][D], t = face_tan_of_mode<K>(n, D);
+        constexpr double pv = (side == 0 || ed % 2 == 0) ? 1.0 : -1.0;
+        constexpr double dv = (side == 0 || ed % 2 == 1 ? 1.0 : -1.0) * 0.5 * ed * (ed + 1);
+        const T c = q[(long long)(v * NM + n) * N + cell];
+        ct[side][v][t] += T(pv) * c;
+        if constexpr (ed > 0) cn[side][v][t] += T(dv) * c;
+      });
+  });
   T acc[5 * NF][NT];
 #pragma unroll
   for (int r = 0; r < 5 * NF; ++r)
 #pragma unroll
     for (int m = 0; m < NT; ++m) acc[r][m] = T(0);
   const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
+  using TB = TanBasisHolder<T, K, NQ>;
+  constexpr TanModes<K> tmd{};
   int bad = 0;
 #pragma unroll 1
   for (int qf = 0; qf < NQ2; ++qf) {
@@ -243,13 +292,13 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
         T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0);
-        static_for<NM>([&](auto nc) {
-          constexpr int n = decltype(nc)::value;
-          const T c = cf[side][vmap[vl]][n];
-          v0 += c * TT::t.B[side][n][qf];
-          if constexpr (md.e[n][D] > 0) vn += c * TT::t.Dn[side][n][qf];
-          if constexpr (md.e[n][T1] > 0) v1 += c * TT::t.D1[side][n][qf];
-          if constexpr (md.e[n][T2] > 0) v2 += c * TT::t.D2[side][n][qf];
+        static_for<NT>([&](auto tc) {
+          constexpr int t = decltype(tc)::value;
+          const T c = ct[side][vmap[vl]][t];
+          v0 += c * TB::t.val[qf][t];
+          if constexpr (tmd.e[t][0] > 0) v1 += c * TB::t.d1[qf][t];
+          if constexpr (tmd.e[t][1] > 0) v2 += c * TB::t.d2[qf][t];
+          if constexpr (t < NT1) vn += cn[side][vmap[vl]][t] * TB::t.val[qf][t];
         });
         qs[vl] = v0;
         dqs[0][vl] = vn * sn;
@@ -397,12 +446,6 @@ __global__ __launch_bounds__(kCellThreads, CellWaves<T>::value) void volume_kern
   const bool act = c < N;
   const long long cc = act ? c : N - 1;  // lanes past the end recompute the last cell, store nothing
 
-  T cf[5][NM];
-#pragma unroll
-  for (int v = 0; v < 5; ++v)
-#pragma unroll
-    for (int n = 0; n < NM; ++n) cf[v][n] = q[(long long)(v * NM + n) * N + cc];
-
   // acc[f][v][n] = sum_q w_q sum_d F^f_d[v](x_q) (2/dx_d) dB_n/dxi_d (x_q), f = F | Ft
   T acc[NF][5][NM];
 #pragma unroll
@@ -411,6 +454,43 @@ __global__ __launch_bounds__(kCellThreads, CellWaves<T>::value) void volume_kern
     for (int v = 0; v < 5; ++v)
 #pragma unroll
       for (int n = 0; n < NM; ++n) acc[f][v][n] = T(0);
+  // Surface terms first (only the accumulators are live, so the record loads
+  // of a wavefront can all be in flight): the upper face of the cell (its own
+  // record) minus the lower face (record of the neighbour below) with the
+  // parity sign of B_n at xi_d = -1, summed in T (a difference of two nearby
+  // records is exact in T).
+  const auto& mt = ModeTabHolder<K>::t;
+  const long long ntile = (N + 63) >> 6;
+  static_for<3>([&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    const T ix = T(g.inv_dx[d]);
+    const T* pu = rec + rec_index(d, cc, 0, RECN, ntile);
+    const T* pl = rec + rec_index(d, (long long)nb32(unsigned(cc), d, -1, g), 0, RECN, ntile);
+    static_for<NF>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        static_for<NT>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          const int r = (f * 5 + v) * NT + m;
+          const T ru = pu[r * 64], rl = pl[r * 64];
+          const T dm = ix * (rl - ru), dp = -ix * (rl + ru);
+          static_for<NM>([&](auto nc) {
+            constexpr int n = decltype(nc)::value;
+            if constexpr (face_tan_of_mode<K>(n, d) == m) acc[f][v][n] += (md.e[n][d] & 1) ? dp : dm;
+          });
+        });
+      }
+    });
+  });
+
+  // the cell's coefficients, then the volume term
+  T cf[5][NM];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int n = 0; n < NM; ++n) cf[v][n] = q[(long long)(v * NM + n) * N + cc];
+
   const T sc[3] = {T(g.two_inv_dx[0]), T(g.two_inv_dx[1]), T(g.two_inv_dx[2])};
   using PB = PointBasisHolder<T, K, NQ>;
   int bad = 0;
@@ -460,34 +540,7 @@ __global__ __launch_bounds__(kCellThreads, CellWaves<T>::value) void volume_kern
   }
   if (bad && act) atomicOr(flag, 1);
 
-  // surface terms: the upper face of the cell (its own record) minus the
-  // lower face (record of the neighbour below) with the parity sign of B_n at
-  // xi_d = -1, added to the volume term in T (a difference of two nearby
-  // records is exact in T); M^{-1} and the stage update in FP64.
-  const auto& mt = ModeTabHolder<K>::t;
-  const long long ntile = (N + 63) >> 6;
-  static_for<3>([&](auto dc) {
-    constexpr int d = decltype(dc)::value;
-    const T ix = T(g.inv_dx[d]);
-    const T* pu = rec + rec_index(d, cc, 0, RECN, ntile);
-    const T* pl = rec + rec_index(d, (long long)nb32(unsigned(cc), d, -1, g), 0, RECN, ntile);
-    static_for<NF>([&](auto fc) {
-      constexpr int f = decltype(fc)::value;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        static_for<NT>([&](auto mc) {
-          constexpr int m = decltype(mc)::value;
-          const int r = (f * 5 + v) * NT + m;
-          const T ru = pu[r * 64], rl = pl[r * 64];
-          const T dm = ix * (rl - ru), dp = -ix * (rl + ru);
-          static_for<NM>([&](auto nc) {
-            constexpr int n = decltype(nc)::value;
-            if constexpr (face_tan_of_mode<K>(n, d) == m) acc[f][v][n] += (md.e[n][d] & 1) ? dp : dm;
-          });
-        });
-      }
-    });
-  });
+  // M^{-1} and the stage update in FP64
   if (!act) return;
   const double dt = out.dt;
 #pragma unroll

@@ -90,7 +90,7 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
     L.adj_qsbar = take(state * 8);
     L.adj_Lbar = take(state * 8);
     L.adj_Ltbar = take(state * 8);
-    L.adj_frec = take(3 * N * 2 * 5 * nm * 8);  // per face: cotangents of both cells' coefficients
+    L.adj_frec = take(3 * 2 * ((N + 63) / 64 * 64) * 5 * nm * 8);  // per face: cotangents of both cells' coefficients
     L.adj_mu = take(adj_mu_slots(N) * 8);
     L.adj_tmp = take(kAlign);
   }

@@ -104,21 +104,17 @@ DGK_HD bool unphysical(const Prim<T>& s) {
 }
 
 // Moments <u^n>, n = 0..6, of the normalised Maxwellian in u over the half
-// line u > 0 (side > 0) or u < 0: the first two from erfc and the Gaussian at
-// u = 0, then <u^{n+2}> = U <u^{n+1}> + (n+1) th <u^n> (integration by parts).
+// line sg u > 0 (sg = +1: u > 0, sg = -1: u < 0): the first two from erfc and
+// the Gaussian at u = 0, then <u^{n+2}> = U <u^{n+1}> + (n+1) th <u^n>
+// (integration by parts).
 template <class T>
-DGK_HD void mom_half(T U, T th, int side, T* m) {
+DGK_HD void mom_half(T U, T th, T sg, T* m) {
   const T r = d_rsqrt(T(2) * th);  // sqrt(lambda)
   const T a = U * r;
   // exp(-lambda U^2) / (2 sqrt(pi lambda)) = exp(-a^2) th r / sqrt(pi)
   const T e = d_exp_bulk(-a * a) * (th * r * T(0.56418958354775628695));
-  if (side > 0) {
-    m[0] = T(0.5) * d_erfc(-a);
-    m[1] = U * m[0] + e;
-  } else {
-    m[0] = T(0.5) * d_erfc(a);
-    m[1] = U * m[0] - e;
-  }
+  m[0] = T(0.5) * d_erfc(-sg * a);
+  m[1] = U * m[0] + sg * e;
 #pragma unroll
   for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + T(n + 1) * th * m[n];
 }
@@ -407,9 +403,9 @@ DGK_HD void sym_mv_acc(const T S[15], const T x[5], T r, T y[5]) {
   y[4] += r * (S[4] * x[0] + S[8] * x[1] + S[11] * x[2] + S[13] * x[3] + S[14] * x[4]);
 }
 
-// SIDE = +1: lower cell (half space u > 0); SIDE = -1: upper cell (u < 0).
-template <int SIDE, class T>
-DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>& acc, int& bad) {
+// sg = +1: lower cell (half space u > 0); sg = -1: upper cell (u < 0).
+template <class T>
+DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>& acc, int& bad, T sg) {
   const T K = T(ph.K), gm1 = T(ph.gm1);
   const Prim<T> s = primitive(q, gm1);
   bad |= int(unphysical(s));
@@ -429,7 +425,7 @@ DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>
   S(b, A);
   // half-space moments of the normal velocity, transverse Gaussian moments
   T M[7];
-  mom_half(s.U, s.th, SIDE, M);
+  mom_half(s.U, s.th, sg, M);
   const Transverse<T> tr(s.V, s.W, s.th, K);
   const T r = s.rho;
   T H[15];
@@ -502,8 +498,8 @@ DGK_HD void face_flux_local(const Phys& ph, const T qL[5], const T dqL[3][5], co
                             T F[5], T Ft[5], int& bad) {
   FaceAcc<T> acc;
   face_acc_zero(acc);
-  face_side<+1>(ph, qL, dqL, acc, bad);
-  face_side<-1>(ph, qR, dqR, acc, bad);
+  face_side(ph, qL, dqL, acc, bad, T(1));
+  face_side(ph, qR, dqR, acc, bad, T(-1));
   face_finish<T, NEED_F>(ph, acc, F, Ft, bad);
 }
 

@@ -66,13 +66,12 @@ DGK_HD void mom_rec_bwd(T U, T th, const T* m, T* mb, T& Ub, T& thb) {
 }
 
 template <class T>
-DGK_HD void mom_half_bwd(T U, T th, int side, const T* m, T* mb, T& Ub, T& thb) {
+DGK_HD void mom_half_bwd(T U, T th, T sg, const T* m, T* mb, T& Ub, T& thb) {
   mom_rec_bwd(U, th, m, mb, Ub, thb);
   const T r = d_rsqrt(T(2) * th);
   const T a = U * r;
   const T E = d_exp_bulk(-a * a);
   const T c0 = T(0.56418958354775628695);  // 1/sqrt(pi)
-  const T sg = side > 0 ? T(1) : T(-1);
   // m1 = U m0 + sg e
   Ub += m[0] * mb[1];
   mb[0] += U * mb[1];
@@ -578,9 +577,9 @@ DGK_HD void sym_mv_bwd(const T S[15], const T x[5], T r, const T yb[5], T Sb[15]
 
 // Reverse of face_side (moment-matrix form).  Adds the cotangents of the
 // side's trace (q, dq) given those of its accumulator contributions.
-template <int SIDE, class T>
+template <class T>
 DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const FaceAcc<T>& accb, T qb[5],
-                              T dqb[3][5]) {
+                          T dqb[3][5], T sg) {
   const T K = T(ph.K), gm1 = T(ph.gm1), inv_k3 = T(ph.inv_k3);
   const Prim<T> s = primitive(q, gm1);
   const Solver5<T> S(s, K, inv_k3);
@@ -597,7 +596,7 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
   for (int k = 0; k < 5; ++k) bA[k] = dtq[k] * ir;
   S(bA, A);
   T M[7];
-  mom_half(s.U, s.th, SIDE, M);
+  mom_half(s.U, s.th, sg, M);
   const Transverse<T> tr(s.V, s.W, s.th, K);
   const T r = s.rho;
 
@@ -654,7 +653,7 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
   Prim<T> sb = prim_zero<T>();
   sb.rho += rb;
   transverse_bwd(tr, s.th, K, trb, sb.V, sb.W, sb.th);
-  mom_half_bwd(s.U, s.th, SIDE, M, Mb, sb.U, sb.th);
+  mom_half_bwd(s.U, s.th, sg, M, Mb, sb.U, sb.th);
   // time slope A = S(dt/rho), dt = -sum_e J_e dq_e
   Solver5Bar<T> Sb;
   T bAb[5], dtqb[5];

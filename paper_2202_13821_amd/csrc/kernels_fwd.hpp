@@ -70,35 +70,6 @@ DGK_D double gauss_w(int i) {
   return r;
 }
 
-// Tables of the volume projection: B[kk][n] = w_q dB_n/dxi_d (x_q) with
-// kk = 3 q + d, q = (qz NQ + qy) NQ + qx (rows padded to a multiple of 4 and
-// columns to 16 with zeros).
-template <class T, int K, int NQ>
-struct VolTab {
-  static constexpr int NM = nmodes(K);
-  static constexpr int KK = NQ * NQ * NQ * 3;
-  static constexpr int KS = (KK + 3) / 4;
-  T B[KS * 4][16];
-  constexpr VolTab() : B{} {
-    constexpr Modes<K> md{};
-    for (int q = 0; q < NQ * NQ * NQ; ++q) {
-      int qx = q % NQ, qy = (q / NQ) % NQ, qz = q / (NQ * NQ);
-      double x[3] = {Gauss<NQ>::x[qx], Gauss<NQ>::x[qy], Gauss<NQ>::x[qz]};
-      double w = Gauss<NQ>::w[qx] * Gauss<NQ>::w[qy] * Gauss<NQ>::w[qz];
-      for (int d = 0; d < 3; ++d)
-        for (int n = 0; n < NM; ++n) {
-          double v = w;
-          for (int e = 0; e < 3; ++e) v *= (e == d) ? dleg(md.e[n][e], x[e]) : leg(md.e[n][e], x[e]);
-          B[3 * q + d][n] = T(v);
-        }
-    }
-  }
-};
-template <class T, int K, int NQ>
-struct VolTabHolder {
-  static constexpr VolTab<T, K, NQ> t{};
-};
-
 // Per-mode constants for the surface terms and the mass matrix.
 template <int K>
 struct ModeTab {
@@ -164,43 +135,6 @@ struct TanBasis {
 template <class T, int K, int NQ>
 struct TanBasisHolder {
   static constexpr TanBasis<T, K, NQ> t{};
-};
-
-// Trace basis of a face with normal axis D: for side s (0: xi_D = +1, 1: -1)
-// and face point qf = b NQ + a (tangential axes D+1, D+2):
-// value, and reference derivatives along (D, D+1, D+2).
-template <class T, int K, int NQ, int D>
-struct TraceTab {
-  static constexpr int NM = nmodes(K), NQ2 = NQ * NQ;
-  T B[2][NM][NQ2], Dn[2][NM][NQ2], D1[2][NM][NQ2], D2[2][NM][NQ2];
-  constexpr TraceTab() : B{}, Dn{}, D1{}, D2{} {
-    constexpr Modes<K> md{};
-    for (int s = 0; s < 2; ++s)
-      for (int n = 0; n < NM; ++n)
-        for (int b = 0; b < NQ; ++b)
-          for (int a = 0; a < NQ; ++a) {
-            const int ed = md.e[n][D], e1 = md.e[n][(D + 1) % 3], e2 = md.e[n][(D + 2) % 3];
-            const double xd = s == 0 ? 1.0 : -1.0, xa = Gauss<NQ>::x[a], xb = Gauss<NQ>::x[b];
-            const int qf = b * NQ + a;
-            B[s][n][qf] = T(leg(ed, xd) * leg(e1, xa) * leg(e2, xb));
-            Dn[s][n][qf] = T(dleg(ed, xd) * leg(e1, xa) * leg(e2, xb));
-            D1[s][n][qf] = T(leg(ed, xd) * dleg(e1, xa) * leg(e2, xb));
-            D2[s][n][qf] = T(leg(ed, xd) * leg(e1, xa) * dleg(e2, xb));
-          }
-  }
-};
-template <class T, int K, int NQ, int D>
-struct TraceTabHolder {
-  static constexpr TraceTab<T, K, NQ, D> t{};
-};
-
-// Blocking of the adjoint face kernel: FPW = 64/NQ^2 faces per wavefront,
-// one lane per face point, 4 wavefronts per block.
-template <int K, int NQ>
-struct FaceCfg {
-  static constexpr int NM = nmodes(K), NT = ntan(K), NQ2 = NQ * NQ;
-  static constexpr int FPW = 64 / NQ2, FPB = 4 * FPW;
-  static constexpr int CS = 5 * NM + 1;  // LDS stride of one cell's coefficients
 };
 
 // Cell-per-lane kernels: 4 wavefronts per block.
@@ -305,7 +239,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
         dqs[1][vl] = v1 * s1;
         dqs[2][vl] = v2 * s2;
       }
-      face_side<side == 0 ? +1 : -1>(ph, qs, dqs, fa, bad);
+      face_side(ph, qs, dqs, fa, bad, T(side == 0 ? 1 : -1));
     });
     T F[5], Ft[5];
     face_finish<T, NEED_F>(ph, fa, F, Ft, bad);
@@ -382,16 +316,6 @@ struct VolOut {
   double* L;         // MODE 2
   double* Lt;        // MODE 2
   double dt;
-};
-
-// Blocking of the adjoint volume kernel: CPB = 64/NQ^2 cells, NQ wavefronts,
-// one lane per volume point.
-template <int K, int NQ>
-struct VolCfg {
-  static constexpr int NM = nmodes(K), NT = ntan(K), NQ2 = NQ * NQ, NQ3 = NQ * NQ * NQ;
-  static constexpr int CPB = 64 / NQ2, NW = NQ, NTH = 64 * NQ;
-  static constexpr int KK = NQ3 * 3, KS = (KK + 3) / 4;
-  static constexpr int CS = 5 * NM + 1;
 };
 
 // Minimum waves per SIMD requested from the register allocator for the

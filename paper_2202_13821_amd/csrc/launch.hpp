@@ -108,16 +108,14 @@ int run_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* 
 template <class T, int K, int NQ, int STAGE>
 int launch_adj_stage(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, double* out, const Geo& g,
                      const Phys& ph) {
-  using FC = FaceCfg<K, NQ>;
-  using VC = VolCfg<K, NQ>;
   const long long N = g.ncell;
-  const unsigned bpd = (unsigned)((N + FC::FPB - 1) / FC::FPB);
-  const unsigned nvb = (unsigned)((N + VC::CPB - 1) / VC::CPB);
+  const unsigned nbf = (unsigned)((N + kAdjFaceThreads / 2 - 1) / (kAdjFaceThreads / 2));
+  const unsigned nbv = (unsigned)((N + kCellThreads - 1) / kCellThreads);
   double* frec = (double*)(c->ws + c->lay.adj_frec);
   double* mu = (double*)(c->ws + c->lay.adj_mu);
-  DG_LAUNCH(c, 3, (adj_face_kernel<T, K, NQ, STAGE><<<dim3(bpd, 3), 256, 0, c->stream>>>(qin, in, frec, g, ph, mu)));
-  DG_LAUNCH(c, 4, (adj_volume_kernel<T, K, NQ, STAGE><<<dim3(nvb), VC::NTH, 0, c->stream>>>(
-                      qin, in, frec, out, g, ph, mu, 3LL * bpd)));
+  DG_LAUNCH(c, 3, (adj_face_kernel<T, K, NQ, STAGE><<<dim3(3 * nbf), kAdjFaceThreads, 0, c->stream>>>(qin, in, frec, g, ph, mu)));
+  DG_LAUNCH(c, 4, (adj_volume_kernel<T, K, NQ, STAGE><<<dim3(nbv), kCellThreads, 0, c->stream>>>(
+                      qin, in, frec, out, g, ph, mu, 3LL * nbf)));
   return DG_HGKS_OK;
 }
 

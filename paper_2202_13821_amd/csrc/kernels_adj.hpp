@@ -148,7 +148,22 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
       if constexpr (NEED_F) pb[0][v][t] += T(w * lb);
       pb[NF - 1][v][t] += T(w * ltb);
     });
-  pair_sum(&pb[0][0][0], NF * 5 * NT);
+  // Record cotangent summed over the pair.  Stage 1: lane 0 keeps the F part
+  // and lane 1 the Ft part (each point's Fbar and Ftbar are then exchanged);
+  // stage 2 has the Ft part only and both lanes keep it.
+  T ph_[5][NT];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if constexpr (NEED_F) {
+        const T send = side ? pb[0][v][t] : pb[1][v][t];
+        const T keep = side ? pb[1][v][t] : pb[0][v][t];
+        ph_[v][t] = keep + pair_swap(send);
+      } else {
+        ph_[v][t] = pb[0][v][t] + pair_swap(pb[0][v][t]);
+      }
+    }
 
   // cotangents of ct, cn
   T ctb[5][NT], cnb[5][NT1];
@@ -198,15 +213,17 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
     T Fb[5], Ftb[5];
 #pragma unroll
     for (int vl = 0; vl < 5; ++vl) {
-      T sf = T(0), st = T(0);
+      T sp = T(0);
 #pragma unroll
-      for (int m = 0; m < NT; ++m) {
-        const T p_ = FT::t.phi[m][qf];
-        if constexpr (NEED_F) sf += p_ * pb[0][vmap[vl]][m];
-        st += p_ * pb[NF - 1][vmap[vl]][m];
+      for (int m = 0; m < NT; ++m) sp += FT::t.phi[m][qf] * ph_[vmap[vl]][m];
+      if constexpr (NEED_F) {
+        const T other = pair_swap(sp);
+        Fb[vl] = side ? other : sp;
+        Ftb[vl] = side ? sp : other;
+      } else {
+        Fb[vl] = T(0);
+        Ftb[vl] = sp;
       }
-      Fb[vl] = sf;
-      Ftb[vl] = st;
     }
     FaceAcc<T> accb;
     face_acc_zero(accb);

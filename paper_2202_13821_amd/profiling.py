@@ -3,6 +3,12 @@
 python -m paper_2202_13821_amd.profiling stats  <kernel_stats.csv>  <out.md>  "<command>"
 python -m paper_2202_13821_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv>
                                                   <out.json> "<command fetch>" "<command write>"
+python -m paper_2202_13821_amd.profiling counters <out.md> "<command prefix>" <counter_collection.csv>...
+
+`counters` summarises SQ/GRBM counter passes per kernel: VALU instructions
+per wavefront, VALU issue utilisation (VALU instructions x 4 cycles over
+4 SIMDs x 256 CUs x the kernel's GRBM_GUI_ACTIVE cycles / 8 XCDs), resident
+wavefronts per SIMD, and the fraction of wave time spent waiting.
 
 `traffic` reads FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of every kernel,
 takes the plain device copy launched by `bench.py --copy-calibration`
@@ -114,8 +120,37 @@ def traffic(fetch_csv, write_csv, out_json, cmd_fetch, cmd_write, copy_bytes=1 <
     return out
 
 
+def counters(out_md, command, *csvs):
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in csvs:
+        for r in _rows(path):
+            vals[short_name(_col(r, "Kernel_Name", "Kernel-Name"))][_col(r, "Counter_Name", "Counter-Name").strip()].append(
+                float(_col(r, "Counter_Value", "Counter-Value")))
+    avg = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in vals.items()}
+    lines = ["# rocprofv3 counters per kernel", "", f"Command (one run per counter set): `{command}`", "",
+             "| kernel | VALU instr / wave | VALU issue util. | waves / SIMD | wait fraction | FP32 flop / wave | FP64 flop / wave |",
+             "|---|---|---|---|---|---|---|"]
+    for k in sorted(avg):
+        d = avg[k]
+        if not k.startswith(("face_kernel", "volume_kernel", "adj_")) or "SQ_WAVES" not in d:
+            continue
+        w = d["SQ_WAVES"]
+        cyc = d.get("GRBM_GUI_ACTIVE", 0.0) / 8.0  # summed over the 8 XCDs
+        valu = d.get("SQ_INSTS_VALU", 0.0)
+        util = valu * 4.0 / (4 * 256 * cyc) if cyc else float("nan")
+        occ = 4.0 * d["SQ_WAVE_CYCLES"] / cyc / 1024.0 if cyc and "SQ_WAVE_CYCLES" in d else float("nan")
+        wait = d["SQ_WAIT_ANY"] / d["SQ_WAVE_CYCLES"] if "SQ_WAIT_ANY" in d else float("nan")
+        f32 = 64 * d.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0) / w
+        f64 = 64 * d.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) / w
+        lines.append(f"| `{k}` | {valu / w:.0f} | {util:.2f} | {occ:.2f} | {wait:.2f} | {f32:.3g} | {f64:.3g} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(*sys.argv[2:7]), indent=1))
+    elif sys.argv[1] == "counters":
+        counters(*sys.argv[2:])

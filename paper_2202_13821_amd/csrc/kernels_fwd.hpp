@@ -159,9 +159,21 @@ DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
 // tangential modes accumulated in registers.  Each record component is then
 // stored as one row of the tile.
 // --------------------------------------------------------------------------
+// LDS of one face block (each lane uses only its own column, so no barrier
+// is needed): the upper cell's face-restricted coefficients, and in stage 1
+// the F part of the record accumulators, in stage 2 the lower cell's trace
+// coefficients.  At 2 x 256 lanes per CU this is 80 floats per lane.
+template <class T, int K, bool NEED_F>
+struct FaceLds {
+  static constexpr int NT = ntan(K), NT1 = ntan(K - 1);
+  static constexpr int NC = 5 * (NT + NT1);
+  T c1[NC][kCellThreads];
+  T x[5 * NT][kCellThreads];
+};
+
 template <class T, int K, int NQ, bool NEED_F, int D>
 DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
-                     long long f) {
+                     long long f, FaceLds<T, K, NEED_F>& sm) {
   constexpr int NM = nmodes(K), NT = ntan(K), NT1 = ntan(K - 1), NQ2 = NQ * NQ;
   constexpr int NF = NEED_F ? 2 : 1;
   constexpr int RECN = 5 * NF * NT;
@@ -170,6 +182,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
   // local frame: velocity (normal, t1, t2) = global (D, T1, T2)
   constexpr int vmap[5] = {0, 1 + D, 1 + T1, 1 + T2, 4};
   using FT = FaceTabHolder<T, K, NQ>;
+  const int tid = threadIdx.x;
   const long long N = g.ncell;
   const bool act = f < N;
   const long long fl = act ? f : N - 1;  // lanes past the end recompute the last face, store nothing
@@ -177,46 +190,67 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
 
   // The traces on this face depend on a cell's modes only through their
   // values at xi_D = +-1: per side s and variable, the tangential-mode
-  // coefficients of the trace, ct[s][v][t] = sum_{e_D} c[v][n(e_D, t)] P_{e_D}(+-1),
-  // and of its normal derivative, cn[s][v][t] = sum_{e_D} c[v][n] P'_{e_D}(+-1)
+  // coefficients of the trace, ct[v][t] = sum_{e_D} c[v][n(e_D, t)] P_{e_D}(+-1),
+  // and of its normal derivative, cn[v][t] = sum_{e_D} c[v][n] P'_{e_D}(+-1)
   // (tangential degree <= K - 1), with P_e(+1) = 1, P_e(-1) = (-1)^e,
   // P'_e(+1) = e(e+1)/2, P'_e(-1) = (-1)^(e+1) e(e+1)/2.
-  T ct[2][5][NT], cn[2][5][NT1];
-#pragma unroll
-  for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) ct[sd][v][t] = T(0);
-#pragma unroll
-      for (int t = 0; t < NT1; ++t) cn[sd][v][t] = T(0);
-    }
+  // Side 1 (upper cell) goes to LDS; side 0 (lower cell) stays in registers,
+  // except its trace coefficients ct in stage 2.
+  T ct0[5][NT], cn0[5][NT1];
   static_for<2>([&](auto sc) {
     constexpr int side = decltype(sc)::value;
     const long long cell = side ? fu : fl;
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+    for (int v = 0; v < 5; ++v) {
+      T ct[NT], cn[NT1];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) ct[t] = T(0);
+#pragma unroll
+      for (int t = 0; t < NT1; ++t) cn[t] = T(0);
       static_for<NM>([&](auto nc) {
         constexpr int n = decltype(nc)::value;
         constexpr int ed = md.e[n][D], t = face_tan_of_mode<K>(n, D);
         constexpr double pv = (side == 0 || ed % 2 == 0) ? 1.0 : -1.0;
         constexpr double dv = (side == 0 || ed % 2 == 1 ? 1.0 : -1.0) * 0.5 * ed * (ed + 1);
         const T c = q[(long long)(v * NM + n) * N + cell];
-        ct[side][v][t] += T(pv) * c;
-        if constexpr (ed > 0) cn[side][v][t] += T(dv) * c;
+        ct[t] += T(pv) * c;
+        if constexpr (ed > 0) cn[t] += T(dv) * c;
       });
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if constexpr (side == 1)
+          sm.c1[v * NT + t][tid] = ct[t];
+        else if constexpr (NEED_F)
+          ct0[v][t] = ct[t];
+        else
+          sm.x[v * NT + t][tid] = ct[t];
+      }
+#pragma unroll
+      for (int t = 0; t < NT1; ++t) {
+        if constexpr (side == 0)
+          cn0[v][t] = cn[t];
+        else
+          sm.c1[5 * NT + v * NT1 + t][tid] = cn[t];
+      }
+    }
   });
-  T acc[5 * NF][NT];
+  // record accumulators: Ft part in registers, F part (stage 1) in LDS
+  T acc[5][NT];
 #pragma unroll
-  for (int r = 0; r < 5 * NF; ++r)
+  for (int r = 0; r < 5; ++r)
 #pragma unroll
-    for (int m = 0; m < NT; ++m) acc[r][m] = T(0);
+    for (int m = 0; m < NT; ++m) {
+      acc[r][m] = T(0);
+      if constexpr (NEED_F) sm.x[r * NT + m][tid] = T(0);
+    }
   const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
   using TB = TanBasisHolder<T, K, NQ>;
   constexpr TanModes<K> tmd{};
   int bad = 0;
 #pragma unroll 1
   for (int qf = 0; qf < NQ2; ++qf) {
+    // keeps the LDS data in LDS: no load or store moves across this point
+    __asm__ __volatile__("" ::: "memory");
     FaceAcc<T> fa;
     face_acc_zero(fa);
     static_for<2>([&](auto sc) {
@@ -228,11 +262,24 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
         T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0);
         static_for<NT>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
-          const T c = ct[side][vmap[vl]][t];
+          T c;
+          if constexpr (side == 1)
+            c = sm.c1[vmap[vl] * NT + t][tid];
+          else if constexpr (NEED_F)
+            c = ct0[vmap[vl]][t];
+          else
+            c = sm.x[vmap[vl] * NT + t][tid];
           v0 += c * TB::t.val[qf][t];
           if constexpr (tmd.e[t][0] > 0) v1 += c * TB::t.d1[qf][t];
           if constexpr (tmd.e[t][1] > 0) v2 += c * TB::t.d2[qf][t];
-          if constexpr (t < NT1) vn += cn[side][vmap[vl]][t] * TB::t.val[qf][t];
+          if constexpr (t < NT1) {
+            T cnv;
+            if constexpr (side == 0)
+              cnv = cn0[vmap[vl]][t];
+            else
+              cnv = sm.c1[5 * NT + vmap[vl] * NT1 + t][tid];
+            vn += cnv * TB::t.val[qf][t];
+          }
         });
         qs[vl] = v0;
         dqs[0][vl] = vn * sn;
@@ -249,23 +296,27 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       const T p = FT::t.phi[m][qf];
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
-        if constexpr (NEED_F) acc[vmap[vl]][m] += p * F[vl];
-        acc[(NF - 1) * 5 + vmap[vl]][m] += p * Ft[vl];
+        if constexpr (NEED_F) sm.x[vmap[vl] * NT + m][tid] += p * F[vl];
+        acc[vmap[vl]][m] += p * Ft[vl];
       }
     });
   }
+  __asm__ __volatile__("" ::: "memory");
   if (!act) return;
   if (bad) atomicOr(flag, 1);
   T* out = rec + rec_index(D, f, 0, RECN, (N + 63) >> 6);
 #pragma unroll
-  for (int r = 0; r < 5 * NF; ++r)
+  for (int r = 0; r < 5; ++r)
 #pragma unroll
-    for (int m = 0; m < NT; ++m) out[(r * NT + m) * 64] = acc[r][m];
+    for (int m = 0; m < NT; ++m) {
+      if constexpr (NEED_F) out[(r * NT + m) * 64] = sm.x[r * NT + m][tid];
+      out[(((NF - 1) * 5 + r) * NT + m) * 64] = acc[r][m];
+    }
 }
 
 // Minimum waves per SIMD requested for the face kernel (register budget).
 #ifndef DGK_FACE_WAVES_F32
-#define DGK_FACE_WAVES_F32 1
+#define DGK_FACE_WAVES_F32 2
 #endif
 #ifndef DGK_FACE_WAVES_F64
 #define DGK_FACE_WAVES_F64 1
@@ -286,10 +337,11 @@ __global__ __launch_bounds__(kCellThreads, FaceWaves<T>::value) void face_kernel
   const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
   const unsigned d = lb / nb;
   const long long f = (long long)(lb - d * nb) * kCellThreads + threadIdx.x;
+  __shared__ FaceLds<T, K, NEED_F> sm;
   switch (d) {
-    case 0: face_lane<T, K, NQ, NEED_F, 0>(q, rec, g, ph, flag, f); break;
-    case 1: face_lane<T, K, NQ, NEED_F, 1>(q, rec, g, ph, flag, f); break;
-    default: face_lane<T, K, NQ, NEED_F, 2>(q, rec, g, ph, flag, f); break;
+    case 0: face_lane<T, K, NQ, NEED_F, 0>(q, rec, g, ph, flag, f, sm); break;
+    case 1: face_lane<T, K, NQ, NEED_F, 1>(q, rec, g, ph, flag, f, sm); break;
+    default: face_lane<T, K, NQ, NEED_F, 2>(q, rec, g, ph, flag, f, sm); break;
   }
 }
 

@@ -176,7 +176,8 @@ def main():
     import torch
 
     if a.adjoint_only:
-        print(json.dumps({"adjoint": {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64")}}),
+        print(json.dumps({"adjoint": {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64"),
+                                      "fp32_bulk_128": adjoint_ratio("fp32_bulk", n=a.n, nsteps=6, stride=3)}}),
               flush=True)
         return
     n = a.n

@@ -133,6 +133,17 @@ int dg_hgks_point_face_flux(dg_hgks_ctx* ctx, const double* x, int64_t n, int32_
                             double* Ft);
 int dg_hgks_point_volume_flux(dg_hgks_ctx* ctx, const double* x, int64_t n, double* F, double* Ft);
 
+/* Diagnostics of a state q (device float64, layout above) on the volume Gauss
+ * rule, the Taylor-Green quantities of Section 5.3 (FP64 in both precision
+ * modes): out_host[0] = kinetic energy sum_K |K| sum_q w_q |rho U|^2/(2 rho),
+ * out_host[1] = enstrophy sum_K |K| sum_q w_q |curl U|^2/2 (U = rho U / rho,
+ * w_q the Gauss weights normalised to sum 1 per cell).  If grad_ke is not
+ * NULL it receives dE_k/dq (device float64, layout of q; zero for rho E), the
+ * seed of dg_hgks_adjoint for the final-kinetic-energy objective.  The sums
+ * are reduced in a fixed order (deterministic).  Synchronises the stream.
+ * Errors: EINVAL (NULL q or out_host), EHIP. */
+int dg_hgks_diagnostics(dg_hgks_ctx* ctx, const double* q, double* out_host, double* grad_ke);
+
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (clearing earlier records); get_timing synchronises and
  * writes, for up to n kernel classes, the summed milliseconds and launch

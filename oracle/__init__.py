@@ -74,6 +74,7 @@ def lib():
             "orc_step_cells": (None, [cp, dp, d, P(i64), i64, dp]),
             "orc_project": (None, [cp, i, dp]),
             "orc_kinetic_energy": (d, [cp, dp]),
+            "orc_enstrophy": (d, [cp, dp]),
             "orc_advection_error": (d, [cp, dp, d, i, i]),
             "orc_step_jvp": (None, [cp, dp, dp, d, d, i, dp, dp]),
             "orc_ke_jvp": (None, [cp, dp, dp, dp, dp]),
@@ -236,6 +237,12 @@ def project(cfg, problem):
 def kinetic_energy(cfg, q):
     q = _f64(q, field_shape(cfg))
     return lib().orc_kinetic_energy(ctypes.byref(cfg), _p(q))
+
+
+def enstrophy(cfg, q):
+    """sum over cells of |K| sum_q w_q |curl U|^2 / 2 on the volume Gauss rule."""
+    q = _f64(q, field_shape(cfg))
+    return lib().orc_enstrophy(ctypes.byref(cfg), _p(q))
 
 
 def advection_error(cfg, q, t, problem="advection", nqe=5):

@@ -1032,6 +1032,39 @@ static R kinetic_energy(const Disc& D, const R* q) {
   return J;
 }
 
+// Enstrophy, sum_K |K| sum_q w_q |omega|^2 / 2 with omega = curl U, U = rho U / rho
+// (the Taylor-Green diagnostic of Section 5.3), from the DG point values and
+// gradients at the volume Gauss points.
+static double enstrophy(const Disc& D, const double* q) {
+  const int nq = D.nq, nm = D.nm;
+  std::vector<double> part(D.ncell);
+#pragma omp parallel for schedule(static)
+  for (int64_t cc = 0; cc < D.ncell; ++cc) {
+    double s = 0.0;
+    for (int qi = 0; qi < nq * nq * nq; ++qi) {
+      int a = qi % nq, b = (qi / nq) % nq, g = qi / (nq * nq);
+      double w = D.wg[a] * D.wg[b] * D.wg[g];
+      double Q[4] = {0, 0, 0, 0}, G[4][3] = {{0}};  // G[v][e] = dQ_v/dx_e
+      for (int v = 0; v < 4; ++v)
+        for (int n = 0; n < nm; ++n) {
+          const double c = q[D.idx(v, n, cc)];
+          Q[v] += c * D.Bv[(size_t)qi * nm + n];
+          for (int e = 0; e < 3; ++e) G[v][e] += c * D.dBv[((size_t)qi * 3 + e) * nm + n] * 2.0 / D.dx[e];
+        }
+      // dU_j/dx_e = (d(rho U_j)/dx_e - U_j drho/dx_e) / rho
+      double dU[3][3];
+      for (int j = 0; j < 3; ++j)
+        for (int e = 0; e < 3; ++e) dU[j][e] = (G[1 + j][e] - Q[1 + j] / Q[0] * G[0][e]) / Q[0];
+      const double ox = dU[2][1] - dU[1][2], oy = dU[0][2] - dU[2][0], oz = dU[1][0] - dU[0][1];
+      s += w * 0.5 * (ox * ox + oy * oy + oz * oz);
+    }
+    part[cc] = s * D.vol;
+  }
+  double E = 0.0;
+  for (int64_t cc = 0; cc < D.ncell; ++cc) E += part[cc];
+  return E;
+}
+
 // L^2 error of the density against the exact advection solution at time t
 // (Section 5.1 error norm, Gaussian quadrature with nqe points per direction).
 static double advection_l2_error(const Disc& D, const double* q, double t, int which, int nqe) {
@@ -1191,6 +1224,11 @@ void orc_project(const Cfg* c, int which, double* q) {
 double orc_kinetic_energy(const Cfg* c, const double* q) {
   Disc D(*c);
   return kinetic_energy(D, q);
+}
+
+double orc_enstrophy(const Cfg* c, const double* q) {
+  Disc D(*c);
+  return enstrophy(D, q);
 }
 
 double orc_advection_error(const Cfg* c, const double* q, double t, int which, int nqe) {

@@ -58,6 +58,7 @@ SIGNATURES = {
     "dg_hgks_check": (ctypes.c_int, [_vp]),
     "dg_hgks_point_face_flux": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp]),
     "dg_hgks_point_volume_flux": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "dg_hgks_diagnostics": (ctypes.c_int, [_vp, _vp, _P(_d), _vp]),
     "dg_hgks_set_timing": (ctypes.c_int, [_vp, _i32]),
     "dg_hgks_get_timing": (ctypes.c_int, [_vp, _P(_d), _P(_i64), _i32]),
     "dg_hgks_last_error": (ctypes.c_char_p, [_vp]),

@@ -13,6 +13,7 @@
 
 #include "dg_hgks.h"
 #include "kernels_adj.hpp"
+#include "kernels_diag.hpp"
 #include "kernels_fwd.hpp"
 #include "runtime.hpp"
 
@@ -83,6 +84,7 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
   L.qstar = take(state * Ts);
   L.P = take(state * 8);
   L.rec = take(3 * ((N + 63) / 64 * 64) * 10 * nt * Ts);  // records padded to whole 64-cell tiles
+  L.diag = take((2 * ((N + dgk::kCellThreads - 1) / dgk::kCellThreads) + 2) * 8);  // diagnostics partial sums
   if (max_stride > 0) {
     L.adj_states = take((size_t)max_stride * state * 8);  // Q^n of each step of a segment
     L.adj_stars = take((size_t)max_stride * state * Ts);  // Q* of each step
@@ -346,6 +348,34 @@ int dg_hgks_point_volume_flux(dg_hgks_ctx* c, const double* x, int64_t n, double
     DG_LAUNCH(c, 1, (point_volume_kernel<float><<<nb, 64, 0, c->stream>>>(x, F, Ft, n, ph, flag)));
   else
     DG_LAUNCH(c, 1, (point_volume_kernel<double><<<nb, 64, 0, c->stream>>>(x, F, Ft, n, ph, flag)));
+  return DG_HGKS_OK;
+}
+
+int dg_hgks_diagnostics(dg_hgks_ctx* c, const double* q, double* out_host, double* grad_ke) {
+  if (!c) return DG_HGKS_EINVAL;
+  if (!q || !out_host) return fail(c, DG_HGKS_EINVAL, "NULL pointer");
+  const Geo g = make_geo(c->p);
+  const long long nb = (g.ncell + kCellThreads - 1) / kCellThreads;
+  double* part = (double*)(c->ws + c->lay.diag);
+  double* sums = part + 2 * nb;
+  const int k = c->p.degree, nq = c->p.nq;
+  auto launch = [&](auto kc, auto nqc) {
+    constexpr int K = decltype(kc)::value, NQ = decltype(nqc)::value;
+    diag_kernel<K, NQ><<<dim3((unsigned)nb), kCellThreads, 0, c->stream>>>(q, g, part, grad_ke);
+  };
+  if (k == 1 && nq == 2)
+    launch(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
+  else if (k == 2 && nq == 3)
+    launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
+  else if (k == 2 && nq == 2)
+    launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+  else
+    return fail(c, DG_HGKS_EUNSUPPORTED, "(degree, nq) combination not compiled");
+  DG_HIP(c, hipGetLastError());
+  diag_reduce_kernel<<<1, 256, 0, c->stream>>>(part, nb, sums);
+  DG_HIP(c, hipGetLastError());
+  DG_HIP(c, hipMemcpyAsync(out_host, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  DG_HIP(c, hipStreamSynchronize(c->stream));
   return DG_HGKS_OK;
 }
 

@@ -116,6 +116,15 @@ class Solver:
         self._chk(self.lib.dg_hgks_point_volume_flux(self.ctx, _ptr(x), n, _ptr(F), _ptr(Ft)))
         return F, Ft
 
+    def diagnostics(self, q, grad=False):
+        """((kinetic energy, enstrophy), dE_k/dq or None) of the state q on the
+        volume Gauss rule (Section 5.3 Taylor-Green diagnostics, FP64)."""
+        q = q.detach().contiguous()
+        out = (ctypes.c_double * 2)()
+        g = torch.empty_like(q) if grad else None
+        self._chk(self.lib.dg_hgks_diagnostics(self.ctx, _ptr(q), out, _ptr(g) if grad else None))
+        return (out[0], out[1]), g
+
     def set_timing(self, enable=True):
         self._chk(self.lib.dg_hgks_set_timing(self.ctx, 1 if enable else 0))
 
@@ -149,34 +158,26 @@ class Solver:
         return torch.empty((max(nslots, 1),) + self.field_shape, dtype=torch.float64, device=self.device)
 
 
+class _KineticEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q, solver):
+        need = bool(ctx.needs_input_grad[0])
+        (ek, _), grad = solver.diagnostics(q, grad=need)
+        if need:
+            ctx.save_for_backward(grad)
+        return torch.tensor(ek, dtype=torch.float64, device=q.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout * grad, None
+
+
 def kinetic_energy(q, solver):
     """Domain-integrated kinetic energy J = sum_K |K| sum_q w_q |rho U|^2/(2 rho)
-    on the volume Gauss rule of the solver (differentiable torch expression,
-    evaluated with the same basis tables as problems.modes)."""
-    import numpy as np
-
-    from .problems import modes
-
-    nq = solver.nq
-    xg, wg = np.polynomial.legendre.leggauss(nq)
-    wg = wg / 2.0
-    md = modes(solver.degree)
-    leg = lambda l, x: np.polynomial.legendre.legval(x, [0.0] * l + [1.0])
-    # B[n][gz][gy][gx]
-    B = np.zeros((len(md), nq, nq, nq))
-    for n, (a, b, c) in enumerate(md):
-        B[n] = leg(c, xg)[:, None, None] * leg(b, xg)[None, :, None] * leg(a, xg)[None, None, :]
-    W = wg[:, None, None] * wg[None, :, None] * wg[None, None, :]
-    Bt = torch.as_tensor(B, dtype=q.dtype, device=q.device)
-    Wt = torch.as_tensor(W, dtype=q.dtype, device=q.device)
-    vals = torch.einsum("vnkji,nabc->vkjiabc", q[:4], Bt)
-    rho = vals[0]
-    ke = (vals[1] ** 2 + vals[2] ** 2 + vals[3] ** 2) / (2.0 * rho)
-    nx, ny, nz = solver.shape
-    vol = 1.0
-    for e, n in enumerate((nx, ny, nz)):
-        vol *= (solver.hi[e] - solver.lo[e]) / n
-    return (ke * Wt).sum() * vol
+    on the volume Gauss rule of the solver, evaluated on the device
+    (dg_hgks_diagnostics), differentiable in q through the device gradient."""
+    return _KineticEnergy.apply(q, solver)
 
 
 class DGHGKSSteps(torch.autograd.Function):

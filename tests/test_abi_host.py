@@ -117,6 +117,9 @@ def test_calls_reject_invalid_arguments_without_device_work():
     assert L.dg_hgks_set_mu(ctx, 0.01) == 0
     assert L.dg_hgks_point_face_flux(ctx, q, 4, 3, 1e-3, q, q) == E
     assert L.dg_hgks_point_volume_flux(ctx, None, 4, q, q) == E
+    out = (ctypes.c_double * 2)()
+    assert L.dg_hgks_diagnostics(ctx, None, out, None) == E
+    assert L.dg_hgks_diagnostics(ctx, q, None, None) == E
     assert L.dg_hgks_destroy(ctx) == 0
     assert L.dg_hgks_destroy(None) == E
 

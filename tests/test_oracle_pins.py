@@ -321,6 +321,77 @@ def test_tgv_initial_kinetic_energy(orc):
     assert abs(Ek - 0.125) < 1e-4
 
 
+def test_tgv_initial_kinetic_energy_converges_to_closed_form(orc):
+    """E_k of the Taylor-Green initial field (rho = 1) is pi^3 on [-pi, pi]^3;
+    the L^2-projected P2 field converges to it at high order."""
+    errs = []
+    for n in (8, 16):
+        c = orc.make_cfg((n, n, n), 2, lo=(-np.pi,) * 3, hi=(np.pi,) * 3)
+        errs.append(abs(orc.kinetic_energy(c, orc.project(c, "tgv")) - np.pi ** 3))
+    assert errs[1] < 1e-3 and errs[0] / errs[1] > 16
+
+
+def test_tgv_initial_enstrophy_converges_to_closed_form(orc):
+    """curl U of the Taylor-Green initial field is (-cos x sin y sin z,
+    -sin x cos y sin z, 2 sin x sin y cos z), so int |curl U|^2 / 2 = 3 pi^3;
+    the P2 gradients converge at second order."""
+    errs = []
+    for n in (8, 16, 32):
+        c = orc.make_cfg((n, n, n), 2, lo=(-np.pi,) * 3, hi=(np.pi,) * 3)
+        errs.append(abs(orc.enstrophy(c, orc.project(c, "tgv")) - 3 * np.pi ** 3))
+    assert errs[2] < 0.2 and errs[0] / errs[1] > 2 and errs[1] / errs[2] > 3
+
+
+def _linear_field(orc, shape, k, lo, hi, rho, grad_u):
+    """Modal coefficients of rho = const and rho U = rho (grad_u @ x), which
+    every P_k (k >= 1) represents exactly: per cell, mode 0 holds the value at
+    the centre and mode e_d (P_1 along axis d) half the cell width times the
+    slope along d."""
+    nm = orc.nmodes(k)
+    modes = orc.modes(k)
+    q = np.zeros((5, nm) + tuple(reversed(shape)))
+    dx = [(hi[d] - lo[d]) / shape[d] for d in range(3)]
+    xc = [lo[d] + (np.arange(shape[d]) + 0.5) * dx[d] for d in range(3)]
+    Z, Y, X = np.meshgrid(xc[2], xc[1], xc[0], indexing="ij")
+    centre = [X, Y, Z]
+    unit = {tuple(int(d == e) for d in range(3)): e for e in range(3)}
+    n_of = {tuple(m): i for i, m in enumerate(modes)}
+    q[0, 0] = rho
+    q[4, 0] = 10.0
+    for j in range(3):
+        q[1 + j, 0] = rho * sum(grad_u[j][e] * centre[e] for e in range(3))
+        for e_vec, e in unit.items():
+            q[1 + j, n_of[e_vec]] = rho * grad_u[j][e] * dx[e] / 2
+    return q
+
+
+def test_enstrophy_and_kinetic_energy_of_linear_fields_exact(orc):
+    """Constant rho and U = A x: curl U = (A32 - A23, A13 - A31, A21 - A12),
+    so the enstrophy is |curl U|^2 V / 2 exactly; the kinetic energy
+    rho int |A x|^2 / 2 over the box is a quadratic the 3-point rule
+    integrates exactly."""
+    lo, hi, shape, rho = (0.0, -1.0, 0.5), (1.0, 1.0, 2.0), (3, 4, 2), 1.7
+    A = np.array([[0.0, -0.8, 0.3], [0.8, 0.1, 0.0], [0.0, 0.45, -0.2]])
+    q = _linear_field(orc, shape, 2, lo, hi, rho, A)
+    c = orc.make_cfg(shape, 2, lo=lo, hi=hi)
+    V = np.prod(np.subtract(hi, lo))
+    w = np.array([A[2, 1] - A[1, 2], A[0, 2] - A[2, 0], A[1, 0] - A[0, 1]])
+    assert abs(orc.enstrophy(c, q) - 0.5 * w @ w * V) < 1e-12 * V
+    # int x_a x_b over the box
+    m1 = [(hi[d] ** 2 - lo[d] ** 2) / 2 for d in range(3)]
+    m2 = [(hi[d] ** 3 - lo[d] ** 3) / 3 for d in range(3)]
+    L = [hi[d] - lo[d] for d in range(3)]
+    Mx = np.empty((3, 3))
+    for a in range(3):
+        for b in range(3):
+            if a == b:
+                Mx[a, b] = m2[a] * np.prod([L[d] for d in range(3) if d != a])
+            else:
+                Mx[a, b] = m1[a] * m1[b] * np.prod([L[d] for d in range(3) if d not in (a, b)])
+    ek = 0.5 * rho * np.trace(A @ Mx @ A.T)
+    assert abs(orc.kinetic_energy(c, q) - ek) < 1e-12 * abs(ek)
+
+
 def test_projection_cell_average(orc):
     c = orc.make_cfg((3, 3, 3), 2, lo=(-np.pi,) * 3, hi=(np.pi,) * 3)
     q = orc.project(c, "tgv")

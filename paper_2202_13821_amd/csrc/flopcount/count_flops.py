@@ -5,7 +5,8 @@ The point functions of gks_point.hpp are compiled for the host to optimised
 LLVM IR (common subexpressions merged, loops unrolled; the code is straight
 line) and their IR instructions are counted: fadd/fsub/fmul = 1 flop,
 llvm.fmuladd/llvm.fma = 2, fdiv = 1, sqrt/exp/erfc = 1 each (also listed
-apart).  The modal evaluation at the point and the projection onto the modes
+apart); vectorisation is disabled, and a vector operation would count once
+per element.  The modal evaluation at the point and the projection onto the modes
 are contractions whose useful flops (non-zero basis entries only) are added
 in closed form (P2, 3 Gauss points per direction, 10 modes, 6 tangential
 modes, 4 modes with a non-zero derivative along each axis).
@@ -24,7 +25,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 def ir():
     out = os.path.join("/tmp", "dg_flopcount.ll")
-    subprocess.run([HIPCC, "--cuda-host-only", "-O2", "-std=c++17", "-ffp-contract=on", "-funroll-loops", "-mllvm", "-unroll-threshold=1000000",
+    subprocess.run([HIPCC, "--cuda-host-only", "-O2", "-std=c++17", "-ffp-contract=on", "-fno-vectorize",
+                    "-fno-slp-vectorize", "-funroll-loops", "-mllvm", "-unroll-threshold=1000000",
                     "-mllvm", "-unroll-max-count=4096", "-S", "-emit-llvm",
                     "-I", os.path.dirname(HERE), "-o", out, os.path.join(HERE, "flopcount.hip")], check=True)
     return open(out).read()
@@ -45,12 +47,15 @@ def count(text, fname, bodies=None):
     c = Counter()
     for line in body.splitlines()[1:]:
         line = line.strip()
+        # vector operations count once per element (<N x float>)
+        vw = re.search(r"<(\d+) x (float|double)>", line)
+        w = int(vw.group(1)) if vw else 1
         if re.search(r"= (fadd|fsub|fmul)\b", line):
-            c["addmul"] += 1
+            c["addmul"] += w
         elif re.search(r"= fdiv\b", line):
-            c["div"] += 1
+            c["div"] += w
         elif "@llvm.fmuladd" in line or "@llvm.fma." in line:
-            c["fma"] += 1
+            c["fma"] += w
         elif re.search(r"@(llvm\.sqrt|sqrtf?\b)", line):
             c["sqrt"] += 1
         elif re.search(r"@(llvm\.exp\.|expf?\b)", line):

@@ -152,30 +152,35 @@ struct Solver5 {
 //   c5 = 2 tau^2 - tau (2 tau + delta) e,        c6 = tau^2 (1 - e),
 // (c5, c6 enter with a minus sign).  The fit F dt + Ft dt^2/2 = FF(dt),
 // F dt/2 + Ft dt^2/8 = FF(dt/2) gives F = sum alpha_i m_i, Ft = sum beta_i m_i.
+// With e = exp(-dt/(2 tau)) (so exp(-dt/tau) = e^2), x = tau/dt,
+// A = 4(1 - e) - (1 - e^2) = (1 - e)(3 - e) and B = 2(1 - e) - (1 - e^2) = (1 - e)^2
+// these are, without cancellation,
+//   alpha = (1 - x A, 2 x tau A + tau (e^2 - 2e - 1), tau (x A - 1), x A,
+//            -2 x tau A - tau (e^2 - 2e), -x tau A),
+//   beta  = (4 x B/dt, 4 x (1 - e)(e - 2 x (1 - e)), 1 - 4 x^2 B, -beta_1,
+//            -beta_2, 4 x^2 B)                        (beta_4 = -beta_1 etc.),
+// so that the finish can combine differences of the equilibrium and
+// non-equilibrium moments.
 // tau = 0 is the inviscid limit (e = 0): F = m1, Ft = m3.
 // x_half = dt / (2 tau) (0 when tau = 0), inv_dt = 1 / dt.
 DGK_HD void time_coefficients(double tau, double x_half, double dt, double inv_dt, double alpha[6], double beta[6]) {
-  const double e2 = tau > 0.0 ? exp(-x_half) : 0.0;
-  const double e1 = e2 * e2;
-  double c[2][6];
-  const double dl[2] = {dt, 0.5 * dt};
-  const double ee[2] = {e1, e2};
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const double d = dl[j], e = ee[j], om = 1.0 - e;
-    c[j][0] = d - tau * om;
-    c[j][1] = 2.0 * tau * tau - tau * d - tau * (2.0 * tau + d) * e;
-    c[j][2] = 0.5 * d * d - tau * d + tau * tau * om;
-    c[j][3] = tau * om;
-    c[j][4] = -(2.0 * tau * tau - tau * (2.0 * tau + d) * e);
-    c[j][5] = -(tau * tau * om);
-  }
-  const double idt = inv_dt, idt2 = 4.0 * idt * idt;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    alpha[i] = (4.0 * c[1][i] - c[0][i]) * idt;
-    beta[i] = (c[0][i] - 2.0 * c[1][i]) * idt2;
-  }
+  const double e = tau > 0.0 ? exp(-x_half) : 0.0;
+  const double x = tau * inv_dt;
+  const double om = 1.0 - e;
+  const double A = om * (3.0 - e), B = om * om;
+  const double xA = x * A, x2B = x * x * B;
+  alpha[0] = 1.0 - xA;
+  alpha[1] = 2.0 * tau * xA + tau * (e * e - 2.0 * e - 1.0);
+  alpha[2] = tau * (xA - 1.0);
+  alpha[3] = xA;
+  alpha[4] = -2.0 * tau * xA - tau * (e * e - 2.0 * e);
+  alpha[5] = -tau * xA;
+  beta[0] = 4.0 * x * B * inv_dt;
+  beta[1] = 4.0 * x * om * (e - 2.0 * x * om);
+  beta[2] = 1.0 - 4.0 * x2B;
+  beta[3] = -beta[0];
+  beta[4] = -beta[1];
+  beta[5] = 4.0 * x2B;
 }
 
 // --------------------------------------------------------------------------
@@ -467,29 +472,27 @@ DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], 
 #pragma unroll
   for (int k = 0; k < 5; ++k) m2[k] = s0.p * ns[k] - m3[k];
 
-  const double ip0 = 1.0 / double(s0.p);
+  const double tau = ph.mu / double(s0.p);
   double al[6], be[6];
-  time_coefficients(ph.mu * ip0, ph.half_dt_over_mu * double(s0.p), ph.dt, ph.inv_dt, al, be);
-  const T* mm[6] = {m1, m2, m3, acc.m4, acc.m5, acc.m6};
+  time_coefficients(tau, ph.half_dt_over_mu * double(s0.p), ph.dt, ph.inv_dt, al, be);
+  // beta_3 = -beta_0, beta_4 = -beta_1, alpha_3 = 1 - alpha_0, alpha_4 = -tau - alpha_1:
+  //   Ft = beta_0 (m1 - m4) + beta_1 (m2 - m5) + beta_2 m3 + beta_5 m6
+  //   F  = m4 + alpha_0 (m1 - m4) + alpha_1 (m2 - m5) - tau m5 + alpha_2 m3 + alpha_5 m6
+  // The equilibrium and non-equilibrium moments nearly cancel in these
+  // differences, which are then exact in T (Sterbenz), so the combination runs
+  // in T with the FP64 coefficients rounded once.
+  const T b0 = T(be[0]), b1 = T(be[1]), b2 = T(be[2]), b5 = T(be[5]);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    double ft = 0.0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) ft += be[j] * double(mm[j][k]);
-    Ft[k] = T(ft);
+    const T d14 = m1[k] - acc.m4[k], d25 = m2[k] - acc.m5[k];
+    Ft[k] = b0 * d14 + b1 * d25 + b2 * m3[k] + b5 * acc.m6[k];
+    if constexpr (NEED_F)
+      F[k] = acc.m4[k] + T(al[0]) * d14 + T(al[1]) * d25 - T(tau) * acc.m5[k] + T(al[2]) * m3[k] + T(al[5]) * acc.m6[k];
   }
   if constexpr (NEED_F) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      double f = 0.0;
-#pragma unroll
-      for (int j = 0; j < 6; ++j) f += al[j] * double(mm[j][k]);
-      F[k] = T(f);
-    }
     // Prandtl fix: the heat flux of -tau g0 (abar.u + Abar) is
     // q = -tau p0 c_p dT0/dn = -mu c_p dT0/dn; add (1/Pr - 1) q.
-    const double q = -ph.mu * ph.cp * double(g.dT[0]);
-    F[4] = T(double(F[4]) + ph.inv_pr_m1 * q);
+    F[4] += T(-ph.inv_pr_m1 * ph.mu * ph.cp) * g.dT[0];
   }
 }
 

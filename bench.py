@@ -212,11 +212,19 @@ def main():
                            "flops_per_launch": w, "avg_launch_ms": face_ms,
                            "flops_per_point": 0.5 * (flops["fp32"]["face_stage1"] + flops["fp32"]["face_stage2"])}
         wv = 0.5 * (flops["fp32"]["volume_stage1"] + flops["fp32"]["volume_stage2"]) * 27 * n ** 3
+        vt = measured_traffic("volume_kernel<float,2,3>")
+        # the stage updates fused into the volume kernel stream Q^n, Q*, P and
+        # Q^{n+1}: 40 B per DOF-update per step in FP32-bulk, 20 B per launch
+        alg_bytes = 20.0 * dof
         out["roofline_volume"] = {"bound": "alu", "achieved": wv / (vol_ms * 1e-3) / 1e12,
                                   "peak": MI355X_PEAK["fp32_vector"], "unit": "TFLOP/s",
                                   "frac": wv / (vol_ms * 1e-3) / 1e12 / MI355X_PEAK["fp32_vector"],
                                   "frac_nonpacked": wv / (vol_ms * 1e-3) / 1e12 / MI355X_PEAK["fp32_vector_nonpacked"],
-                                  "traffic": measured_traffic("volume_kernel<float,2,3>")}
+                                  "traffic": vt,
+                                  "hbm": {"algorithmic_bytes_per_launch": alg_bytes,
+                                          "algorithmic_GBs": alg_bytes / (vol_ms * 1e-3) / 1e9,
+                                          "measured_GBs": (vt / (vol_ms * 1e-3) / 1e9) if vt else None,
+                                          "peak_GBs": MI355X_PEAK["hbm_GBs"]}}
         per_step = flops["per_step_per_cell"]["fp32"] * n ** 3
         out["step_flops"] = per_step
         out["step_tflops"] = per_step / sec32 / 1e12

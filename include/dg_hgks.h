@@ -59,9 +59,10 @@ typedef struct dg_hgks_params {
   uint32_t struct_size; /* sizeof(dg_hgks_params) */
   int32_t nx, ny, nz;   /* cells per axis, >= 1 */
   double lo[3], hi[3];  /* periodic box, hi > lo */
-  int32_t degree;       /* k of the P_k space: 1 or 2 */
+  int32_t degree;       /* k of the P_k space: 1, 2 or 3 */
   int32_t nq;           /* Gauss points per direction; 0 -> degree + 1.
-                           Compiled pairs (degree, nq): (1,2) (2,3) (2,2) */
+                           Compiled pairs (degree, nq): (1,2) (2,3) (2,2)
+                           (3,4) (3,3); nq = degree is the paper's rule */
   double gamma;         /* specific heat ratio > 1; K = (5 - 3 gamma)/(gamma - 1) */
   double mu;            /* dynamic viscosity >= 0, tau = mu / p */
   double prandtl;       /* Prandtl number > 0 */

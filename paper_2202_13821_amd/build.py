@@ -24,7 +24,7 @@ FLAGS = [
 ]
 
 # (precision, degree, Gauss points per axis) compiled into the library
-CONFIGS = [(t, k, nq) for t in ("float", "double") for (k, nq) in ((1, 2), (2, 3), (2, 2))]
+CONFIGS = [(t, k, nq) for t in ("float", "double") for (k, nq) in ((1, 2), (2, 3), (2, 2), (3, 4), (3, 3))]
 
 
 def _units():

@@ -45,7 +45,9 @@ namespace {
 using dgrt::fail;
 using dgrt::Layout;
 
-bool supported(int k, int nq) { return (k == 1 && nq == 2) || (k == 2 && nq == 3) || (k == 2 && nq == 2); }
+bool supported(int k, int nq) {
+  return (k == 1 && nq == 2) || (k == 2 && nq == 3) || (k == 2 && nq == 2) || (k == 3 && nq == 4) || (k == 3 && nq == 3);
+}
 
 int validate(const dg_hgks_params* p, std::string& why) {
   if (!p) { why = "params is NULL"; return DG_HGKS_EINVAL; }
@@ -54,7 +56,7 @@ int validate(const dg_hgks_params* p, std::string& why) {
   if ((long long)p->nx * p->ny * p->nz > (1LL << 31)) { why = "too many cells"; return DG_HGKS_EINVAL; }
   for (int e = 0; e < 3; ++e)
     if (!(p->hi[e] > p->lo[e]) || !std::isfinite(p->hi[e] - p->lo[e])) { why = "need hi > lo on every axis"; return DG_HGKS_EINVAL; }
-  if (p->degree < 1 || p->degree > 2) { why = "degree must be 1 or 2"; return DG_HGKS_EINVAL; }
+  if (p->degree < 1 || p->degree > 3) { why = "degree must be 1, 2 or 3"; return DG_HGKS_EINVAL; }
   const int nq = p->nq ? p->nq : p->degree + 1;
   if (nq < 1 || nq > 4) { why = "nq must be in [1, 4]"; return DG_HGKS_EINVAL; }
   if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) { why = "gamma must be > 1"; return DG_HGKS_EINVAL; }
@@ -113,6 +115,8 @@ int dispatch(const dg_hgks_params& p, F&& f) {
   if (k == 1 && nq == 2) return f32 ? f(Tag<float, 1, 2>{}) : f(Tag<double, 1, 2>{});
   if (k == 2 && nq == 3) return f32 ? f(Tag<float, 2, 3>{}) : f(Tag<double, 2, 3>{});
   if (k == 2 && nq == 2) return f32 ? f(Tag<float, 2, 2>{}) : f(Tag<double, 2, 2>{});
+  if (k == 3 && nq == 4) return f32 ? f(Tag<float, 3, 4>{}) : f(Tag<double, 3, 4>{});
+  if (k == 3 && nq == 3) return f32 ? f(Tag<float, 3, 3>{}) : f(Tag<double, 3, 3>{});
   return DG_HGKS_EUNSUPPORTED;
 }
 
@@ -369,6 +373,10 @@ int dg_hgks_diagnostics(dg_hgks_ctx* c, const double* q, double* out_host, doubl
     launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
   else if (k == 2 && nq == 2)
     launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+  else if (k == 3 && nq == 4)
+    launch(std::integral_constant<int, 3>{}, std::integral_constant<int, 4>{});
+  else if (k == 3 && nq == 3)
+    launch(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
   else
     return fail(c, DG_HGKS_EUNSUPPORTED, "(degree, nq) combination not compiled");
   DG_HIP(c, hipGetLastError());

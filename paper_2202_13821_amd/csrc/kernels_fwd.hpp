@@ -163,17 +163,24 @@ DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
 // is needed): the upper cell's face-restricted coefficients, and in stage 1
 // the F part of the record accumulators, in stage 2 the lower cell's trace
 // coefficients.  At 2 x 256 lanes per CU this is 80 floats per lane.
-template <class T, int K, bool NEED_F>
+template <class T, int K, bool NEED_F, int NTH>
 struct FaceLds {
   static constexpr int NT = ntan(K), NT1 = ntan(K - 1);
   static constexpr int NC = 5 * (NT + NT1);
-  T c1[NC][kCellThreads];
-  T x[5 * NT][kCellThreads];
+  T c1[NC][NTH];
+  T x[5 * NT][NTH];
 };
+
+// Lanes per face block: 256, or 128 where the LDS columns of 256 lanes would
+// exceed the 160 KB of a CU (FP64 at P3).
+template <class T, int K>
+constexpr int face_threads() {
+  return sizeof(FaceLds<T, K, true, kCellThreads>) <= 160 * 1024 ? kCellThreads : kCellThreads / 2;
+}
 
 template <class T, int K, int NQ, bool NEED_F, int D>
 DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
-                     long long f, FaceLds<T, K, NEED_F>& sm) {
+                     long long f, FaceLds<T, K, NEED_F, face_threads<T, K>()>& sm) {
   constexpr int NM = nmodes(K), NT = ntan(K), NT1 = ntan(K - 1), NQ2 = NQ * NQ;
   constexpr int NF = NEED_F ? 2 : 1;
   constexpr int RECN = 5 * NF * NT;
@@ -314,30 +321,26 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
     }
 }
 
-// Minimum waves per SIMD requested for the face kernel (register budget).
-#ifndef DGK_FACE_WAVES_F32
-#define DGK_FACE_WAVES_F32 2
-#endif
-#ifndef DGK_FACE_WAVES_F64
-#define DGK_FACE_WAVES_F64 1
-#endif
-template <class T>
+// Minimum waves per SIMD requested for the face kernel (register budget):
+// two for FP32 up to P2 (the LDS columns then take 80 floats per lane), one
+// otherwise.
+template <class T, int K>
 struct FaceWaves {
-  static constexpr int value = sizeof(T) == 4 ? DGK_FACE_WAVES_F32 : DGK_FACE_WAVES_F64;
+  static constexpr int value = (sizeof(T) == 4 && K <= 2) ? 2 : 1;
 };
 
-// Grid: 3 nb blocks of kCellThreads lanes, nb = ceil(N / kCellThreads); the
-// logical block (after the XCD reordering) picks the normal axis and the
+// Grid: 3 nb blocks of face_threads<T, K>() lanes, nb = ceil(N / lanes);
+// the logical block (after the XCD reordering) picks the normal axis and the
 // range of faces.
 template <class T, int K, int NQ, bool NEED_F>
-__global__ __launch_bounds__(kCellThreads, FaceWaves<T>::value) void face_kernel(const T* __restrict__ q,
-                                                                                T* __restrict__ rec, Geo g,
-                                                                                Phys ph, int* flag) {
+__global__ __launch_bounds__((face_threads<T, K>()), (FaceWaves<T, K>::value)) void face_kernel(
+    const T* __restrict__ q, T* __restrict__ rec, Geo g, Phys ph, int* flag) {
+  constexpr int FT = face_threads<T, K>();
   const unsigned nb = gridDim.x / 3;
   const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
   const unsigned d = lb / nb;
-  const long long f = (long long)(lb - d * nb) * kCellThreads + threadIdx.x;
-  __shared__ FaceLds<T, K, NEED_F> sm;
+  const long long f = (long long)(lb - d * nb) * FT + threadIdx.x;
+  __shared__ FaceLds<T, K, NEED_F, FT> sm;
   switch (d) {
     case 0: face_lane<T, K, NQ, NEED_F, 0>(q, rec, g, ph, flag, f, sm); break;
     case 1: face_lane<T, K, NQ, NEED_F, 1>(q, rec, g, ph, flag, f, sm); break;
@@ -348,12 +351,12 @@ __global__ __launch_bounds__(kCellThreads, FaceWaves<T>::value) void face_kernel
 // --------------------------------------------------------------------------
 // Volume kernel.  One lane per cell, 256 cells per block; every lane of a
 // wavefront visits the same volume point at the same time, so the basis
-// values of the point are wavefront-uniform (scalar loads).  Per point: the
-// trace Q, dQ from the cell's coefficients (registers), the volume flux, and
-// its projection sum_q w_q F_d dB_n/dx_d accumulated in registers over the
-// non-zero entries of dB_n/dxi_d.  Then the six face records of the cell
-// (record layout rec[dir][component][cell]: one coalesced row per component),
-// M^{-1}, and the stage update in FP64.
+// values of the point are wavefront-uniform (scalar loads).  First the six
+// face records of the cell (record tiles: one coalesced row per component),
+// then per point the trace Q, dQ from the cell's coefficients, the volume
+// flux, and its projection sum_q w_q F_d dB_n/dx_d accumulated in registers
+// over the non-zero entries of dB_n/dxi_d; then M^{-1} and the stage update
+// in FP64.
 // MODE 0: stage 1 (F and Ft)   -> Q* (T) and P = Q^n + dt L + dt^2/6 L_t (FP64)
 // MODE 1: stage 2 (Ft only)    -> Q^{n+1} = P + dt^2/3 L_t(Q*) (FP64, + T copy)
 // MODE 2: operator only        -> L, L_t (FP64)
@@ -373,9 +376,9 @@ struct VolOut {
 // Minimum waves per SIMD requested from the register allocator for the
 // volume kernel (FP32: two resident wavefronts per SIMD hide the memory
 // phases; FP64 needs twice the registers).
-template <class T>
+template <class T, int K>
 struct CellWaves {
-  static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+  static constexpr int value = (sizeof(T) == 4 && K <= 2) ? 2 : 1;
 };
 
 // Basis at the volume points, q = (qz NQ + qy) NQ + qx: phi[q][n] = B_n(x_q),
@@ -410,7 +413,7 @@ struct PointBasisHolder {
 };
 
 template <class T, int K, int NQ, int MODE>
-__global__ __launch_bounds__(kCellThreads, CellWaves<T>::value) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,
+__global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,
                                                              Geo g, Phys ph, VolOut<T> out, int* flag) {
   constexpr int NM = nmodes(K), NT = ntan(K), NQ3 = NQ * NQ * NQ;
   constexpr bool NEED_F = (MODE != 1);

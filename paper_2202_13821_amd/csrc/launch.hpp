@@ -34,10 +34,12 @@ int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g,
   int* flag = (int*)(c->ws + c->lay.flag);
   const long long N = g.ncell;
   const unsigned nvb = (unsigned)((N + kCellThreads - 1) / kCellThreads);
+  constexpr int FT = face_threads<T, K>();
+  const unsigned nfb = (unsigned)((N + FT - 1) / FT);
   if constexpr (MODE == 1) {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(3 * nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, flag)));
+    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
   } else {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(3 * nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, flag)));
+    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
   }
   DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE><<<dim3(nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, o, flag)));
   return DG_HGKS_OK;

@@ -58,7 +58,7 @@ def test_workspace_bytes():
 
 BAD = [
     dict(shape=(0, 8, 8)), dict(shape=(8, -1, 8)), dict(lo=(1, 0, 0), hi=(1, 1, 1)), dict(degree=0),
-    dict(degree=3), dict(nq=5), dict(gamma=1.0), dict(gamma=float("nan")), dict(mu=-1e-3),
+    dict(degree=4), dict(nq=5), dict(gamma=1.0), dict(gamma=float("nan")), dict(mu=-1e-3),
     dict(prandtl=0.0), dict(precision=7),
 ]
 

@@ -14,7 +14,8 @@ from paper_2202_13821_amd import kinetic_energy, problems as P
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("k,nq,shape", [(2, 3, (7, 5, 6)), (1, 2, (5, 9, 4)), (2, 2, (6, 4, 5)), (2, 3, (70, 3, 2))])
+@pytest.mark.parametrize("k,nq,shape", [(2, 3, (7, 5, 6)), (1, 2, (5, 9, 4)), (2, 2, (6, 4, 5)), (2, 3, (70, 3, 2)),
+                                        (3, 4, (5, 4, 3)), (3, 3, (4, 6, 5))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
 def test_diagnostics_vs_oracle(k, nq, shape, precision):
     say("diagnostics", k, nq, shape, precision)

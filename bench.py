@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-rules", action="store_true",
+                    help="skip the other compiled (degree, Gauss points) rules: P2 with 2 points, P3 with 3 and 4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-only", action="store_true",
                     help="profiling aid: run only the adjoint/forward timing (32^3) and print it")
@@ -55,14 +57,16 @@ def load_flops():
     return None
 
 
-def time_path(precision, n, steps, warmup, timing=True):
+def time_path(precision, n, steps, warmup, timing=True, k=2, nq=0):
     import torch
 
     from paper_2202_13821_amd import Solver, problems
 
-    q0, lo, hi = problems.tgv((n, n, n), 2)
-    dt = problems.tgv_dt(n)
-    s = Solver((n, n, n), lo, hi, 2, mu=1.0 / 1600.0, prandtl=0.72, precision=precision, device="cuda:0")
+    q0, lo, hi = problems.tgv((n, n, n), k)
+    # P3 runs at a smaller CFL number (the DG limit falls like 1 / (2k + 1))
+    dt = problems.tgv_dt(n, cfl=0.15 if k < 3 else 0.08)
+    s = Solver((n, n, n), lo, hi, k, nq=nq, mu=1.0 / 1600.0, prandtl=0.72, precision=precision,
+               device="cuda:0")
     q = torch.as_tensor(q0, device="cuda:0")
     s.step(q, dt, warmup)
     s.check()
@@ -247,6 +251,19 @@ def main():
         out["rel_l2_fp32_bulk_vs_fp64"] = max(
             float(torch.linalg.norm(d[list(g)]) / torch.linalg.norm(r[list(g)])) for g in groups)
         del s64
+    if not a.no_rules:
+        # the other compiled quadrature rules on the same Taylor-Green workload
+        out["rules"] = {}
+        for k, nq in ((2, 2), (3, 3), (3, 4)):
+            leg = {"degree": k, "gauss_points_per_axis": nq, "modes": (k + 1) * (k + 2) * (k + 3) // 6}
+            dof_k = 5 * leg["modes"] * n ** 3
+            for prec in ("fp32_bulk", "fp64"):
+                sec, kk, qk, sk = time_path(prec, n, min(a.steps, 5), 1, k=k, nq=nq)
+                leg[prec] = {"value": dof_k / sec, "ms_per_step": 1e3 * sec,
+                             "kernels_ms_per_launch": {x: (v[0] / v[1] if v[1] else None) for x, v in kk.items()
+                                                       if x in ("face", "volume")}}
+                del qk, sk
+            out["rules"][f"p{k}_nq{nq}"] = leg
     if not a.no_adjoint:
         out["adjoint"] = {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64"),
                           "fp32_bulk_128": adjoint_ratio("fp32_bulk", n=n, nsteps=6, stride=3)}

@@ -210,3 +210,35 @@ class DGHGKSSteps(torch.autograd.Function):
 
 def steps(q0, mu, solver, dt, nsteps):
     return DGHGKSSteps.apply(q0, mu, solver, dt, nsteps)
+
+
+def tgv_history(solver, q, dt, nsteps, every=1):
+    """Advance q in place by nsteps S2O4 steps of size dt and record, at
+    t = 0, every*dt, 2*every*dt, ... (and at the final time), the kinetic
+    energy and the enstrophy of the state (device diagnostics, FP64), and the
+    kinetic-energy dissipation rate eps = -dE_k/dt from central differences of
+    E_k in time (one-sided at the two ends): the Taylor-Green curves of
+    Section 5.3.  Values are domain integrals; divide by the box volume for
+    the per-volume curves.  For a nearly incompressible flow eps tracks
+    2 (mu / rho) times the enstrophy."""
+    import numpy as np
+
+    if nsteps < 1 or every < 1:
+        raise ValueError("nsteps and every must be >= 1")
+    t, ek, en = [0.0], [], []
+    (e, w), _ = solver.diagnostics(q)
+    ek.append(e)
+    en.append(w)
+    done = 0
+    while done < nsteps:
+        m = min(every, nsteps - done)
+        solver.step(q, dt, m)
+        done += m
+        (e, w), _ = solver.diagnostics(q)
+        t.append(done * dt)
+        ek.append(e)
+        en.append(w)
+    solver.check()
+    t, ek, en = np.array(t), np.array(ek), np.array(en)
+    eps = -np.gradient(ek, t) if len(t) > 2 else -np.diff(ek) / np.diff(t) * np.ones(len(t))
+    return {"t": t, "kinetic_energy": ek, "enstrophy": en, "dissipation": eps}

@@ -259,9 +259,20 @@ def main():
             dof_k = 5 * leg["modes"] * n ** 3
             for prec in ("fp32_bulk", "fp64"):
                 sec, kk, qk, sk = time_path(prec, n, min(a.steps, 5), 1, k=k, nq=nq)
-                leg[prec] = {"value": dof_k / sec, "ms_per_step": 1e3 * sec,
-                             "kernels_ms_per_launch": {x: (v[0] / v[1] if v[1] else None) for x, v in kk.items()
-                                                       if x in ("face", "volume")}}
+                ms = {x: (v[0] / v[1] if v[1] else None) for x, v in kk.items() if x in ("face", "volume")}
+                leg[prec] = {"value": dof_k / sec, "ms_per_step": 1e3 * sec, "kernels_ms_per_launch": ms}
+                fr = (flops or {}).get("rules", {}).get(f"p{k}_nq{nq}", {}).get("fp32" if prec != "fp64" else "fp64")
+                if fr and ms["face"] and ms["volume"]:
+                    peak = MI355X_PEAK["fp64_vector"] if prec == "fp64" else MI355X_PEAK["fp32_vector"]
+                    rl = {"unit": "TFLOP/s", "peak": peak}
+                    for kern, pts in (("face", 3 * nq * nq), ("volume", nq ** 3)):
+                        w = 0.5 * (fr[f"{kern}_stage1"] + fr[f"{kern}_stage2"]) * pts * n ** 3
+                        ach = w / (ms[kern] * 1e-3) / 1e12
+                        rl[kern] = {"achieved": ach, "frac": ach / peak}
+                        if prec != "fp64":
+                            rl[kern]["frac_nonpacked"] = ach / MI355X_PEAK["fp32_vector_nonpacked"]
+                    rl["step_tflops"] = fr["per_step_per_cell"] * n ** 3 / sec / 1e12
+                    leg[prec]["roofline"] = rl
                 del qk, sk
             out["rules"][f"p{k}_nq{nq}"] = leg
     if not a.no_adjoint:

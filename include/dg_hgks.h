@@ -68,6 +68,14 @@ typedef struct dg_hgks_params {
   double prandtl;       /* Prandtl number > 0 */
   int32_t precision;    /* DG_HGKS_FP64 or DG_HGKS_FP32_BULK */
   int32_t reserved;
+  const double* cell_widths; /* NULL: uniform cells (hi - lo) / n.  Otherwise a
+                           host array of nx + ny + nz cell widths (the x widths,
+                           then y, then z) of a separable non-uniform mesh, as
+                           in Section 5.1's mapped meshes: every width finite and
+                           > 0, each axis summing to hi - lo within 1e-10
+                           relative.  Copied by dg_hgks_init (the caller may free
+                           it afterwards) and uploaded to the workspace with the
+                           first launch. */
 } dg_hgks_params;
 
 typedef struct dg_hgks_ctx dg_hgks_ctx;

@@ -24,12 +24,15 @@ class Cfg(ctypes.Structure):
         ("k", ctypes.c_int32), ("nq", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
         ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("widths", ctypes.c_void_p),
     ]
 
 
 def make_cfg(shape, k, nq=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-             gamma=1.4, mu=0.0, prandtl=1.0):
-    """shape = (nx, ny, nz)."""
+             gamma=1.4, mu=0.0, prandtl=1.0, widths=None):
+    """shape = (nx, ny, nz).  widths: optional separable mesh, the nx + ny + nz
+    cell widths (x, then y, then z), each axis summing to hi - lo; None for
+    the uniform mesh."""
     c = Cfg()
     c.nx, c.ny, c.nz = (int(s) for s in shape)
     c.k = int(k)
@@ -38,6 +41,13 @@ def make_cfg(shape, k, nq=None, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
         c.lo[e] = float(lo[e])
         c.hi[e] = float(hi[e])
     c.gamma, c.mu, c.prandtl = float(gamma), float(mu), float(prandtl)
+    c.widths = None
+    if widths is not None:
+        w = np.ascontiguousarray(widths, dtype=np.float64)
+        if w.shape != (c.nx + c.ny + c.nz,) or not np.all(w > 0):
+            raise ValueError("widths: nx + ny + nz positive cell widths")
+        c._widths = w  # keeps the array alive as long as the configuration
+        c.widths = w.ctypes.data
     return c
 
 

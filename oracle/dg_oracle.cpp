@@ -75,6 +75,10 @@ struct Cfg {
   int32_t pad;
   double lo[3], hi[3];
   double gamma, mu, prandtl;
+  // Optional separable mesh (Section 5.1 non-uniform meshes): nx + ny + nz
+  // cell widths (x, then y, then z) summing to hi - lo per axis; NULL for
+  // the uniform mesh dx = (hi - lo) / n.
+  const double* widths;
 };
 
 // ---------------------------------------------------------------------------
@@ -566,8 +570,9 @@ struct Disc {
   std::vector<Mode> md;
   int nm = 0, nq = 0;
   std::vector<double> xg, wg;  // Gauss nodes on [-1,1], weights normalised to sum 1
-  double dx[3] = {0, 0, 0}, vol = 0, area[3] = {0, 0, 0};
-  std::vector<double> mass;  // M_nn by quadrature (exact)
+  // separable mesh: width wd[e][i] and lower node xl[e][i] of cell i along axis e
+  std::vector<double> wd[3], xl[3];
+  std::vector<double> mass;  // M_nn / |K| by quadrature (exact), reference cell
   // basis values at volume points: [q][n], reference gradient [q][d][n]
   std::vector<double> Bv, dBv;
   // face traces: for direction d and side s (0: xi_d=+1, 1: xi_d=-1), face point
@@ -584,9 +589,16 @@ struct Disc {
     gauss_legendre(nq, xg.data(), wg.data());
     for (auto& w : wg) w *= 0.5;
     const int n[3] = {c.nx, c.ny, c.nz};
-    for (int e = 0; e < 3; ++e) dx[e] = (c.hi[e] - c.lo[e]) / n[e];
-    vol = dx[0] * dx[1] * dx[2];
-    for (int e = 0; e < 3; ++e) area[e] = vol / dx[e];
+    for (int e = 0, off = 0; e < 3; off += n[e], ++e) {
+      wd[e].resize(n[e]);
+      xl[e].resize(n[e]);
+      double x = c.lo[e];
+      for (int i = 0; i < n[e]; ++i) {
+        wd[e][i] = c.widths ? c.widths[off + i] : (c.hi[e] - c.lo[e]) / n[e];
+        xl[e][i] = c.widths ? x : c.lo[e] + i * wd[e][i];
+        x += wd[e][i];
+      }
+    }
     ncell = (int64_t)c.nx * c.ny * c.nz;
     // mass matrix diagonal by an exact Gauss rule (k+1 points per direction)
     {
@@ -603,7 +615,7 @@ struct Disc {
               double B = basis(n, xi);
               s += 0.125 * w[a] * w[b] * w[g] * B * B;
             }
-        mass[n] = s * vol;
+        mass[n] = s;
       }
     }
     const int nqv = nq * nq * nq;
@@ -669,6 +681,20 @@ struct Disc {
     k = (int)(cc / ((int64_t)c.nx * c.ny));
   }
   size_t idx(int v, int n, int64_t cc) const { return ((size_t)v * nm + n) * (size_t)ncell + (size_t)cc; }
+  // width of cell cc along axis e, its volume |K| and the area |Gamma_d| of its d-faces
+  double width(int e, int64_t cc) const {
+    int p[3];
+    ijk(cc, p[0], p[1], p[2]);
+    return wd[e][p[e]];
+  }
+  double cvol(int64_t cc) const { return width(0, cc) * width(1, cc) * width(2, cc); }
+  double carea(int d, int64_t cc) const { return cvol(cc) / width(d, cc); }
+  // physical coordinate of the reference point xi in cell cc
+  void xphys(int64_t cc, const double xi[3], double x[3]) const {
+    int p[3];
+    ijk(cc, p[0], p[1], p[2]);
+    for (int e = 0; e < 3; ++e) x[e] = xl[e][p[e]] + (0.5 + 0.5 * xi[e]) * wd[e][p[e]];
+  }
   int64_t neighbor(int64_t cc, int d, int off) const {
     int i, j, k;
     ijk(cc, i, j, k);
@@ -689,7 +715,7 @@ static void eval_point(const Disc& D, const R* q, int64_t cc, const double* B, c
       for (int e = 0; e < 3; ++e) g[e] += qn * R(dB[e * D.nm + n]);
     }
     Q[v] = s;
-    for (int e = 0; e < 3; ++e) dQ[e][v] = g[e] * R(2.0 / D.dx[e]);
+    for (int e = 0; e < 3; ++e) dQ[e][v] = g[e] * R(2.0 / D.width(e, cc));
   }
 }
 
@@ -716,6 +742,7 @@ template <class R>
 static void assemble_cell(const Disc& D, R mu, const R* q, int64_t cc, const R* const Fup[3], const R* const Ftup[3],
                           const R* const Flo[3], const R* const Ftlo[3], R* Lc, R* Ltc) {
   const int nm = D.nm, nq = D.nq, nqf = nq * nq, nqv = nq * nq * nq;
+  const double vol = D.cvol(cc);
   std::vector<R> Rr(5 * nm, R(0.0)), Rt(5 * nm, R(0.0));
   for (int g = 0; g < nq; ++g)
     for (int b = 0; b < nq; ++b)
@@ -727,10 +754,10 @@ static void assemble_cell(const Disc& D, R mu, const R* q, int64_t cc, const R* 
         volume_flux(D.c, mu, Q, dQ, F, Ft);
         for (int n = 0; n < nm; ++n)
           for (int e = 0; e < 3; ++e) {
-            double gB = D.dBv[((size_t)qi * 3 + e) * nm + n] * 2.0 / D.dx[e];
+            double gB = D.dBv[((size_t)qi * 3 + e) * nm + n] * 2.0 / D.width(e, cc);
             for (int v = 0; v < 5; ++v) {
-              Rr[v * nm + n] += R(D.vol * w * gB) * F[e][v];
-              Rt[v * nm + n] += R(D.vol * w * gB) * Ft[e][v];
+              Rr[v * nm + n] += R(vol * w * gB) * F[e][v];
+              Rt[v * nm + n] += R(vol * w * gB) * Ft[e][v];
             }
           }
       }
@@ -740,21 +767,22 @@ static void assemble_cell(const Disc& D, R mu, const R* q, int64_t cc, const R* 
       for (int aq = 0; aq < nq; ++aq) {
         int qf = bq * nq + aq;
         double w = D.wg[aq] * D.wg[bq];
+        const double area = D.carea(d, cc);
         for (int n = 0; n < nm; ++n) {
           double Bup = D.Bf[(((size_t)d * 2 + 0) * nqf + qf) * nm + n];
           double Blo = D.Bf[(((size_t)d * 2 + 1) * nqf + qf) * nm + n];
           for (int v = 0; v < 5; ++v) {
-            Rr[v * nm + n] -= R(D.area[d] * w * Bup) * Fup[d][qf * 5 + v];
-            Rr[v * nm + n] += R(D.area[d] * w * Blo) * Flo[d][qf * 5 + v];
-            Rt[v * nm + n] -= R(D.area[d] * w * Bup) * Ftup[d][qf * 5 + v];
-            Rt[v * nm + n] += R(D.area[d] * w * Blo) * Ftlo[d][qf * 5 + v];
+            Rr[v * nm + n] -= R(area * w * Bup) * Fup[d][qf * 5 + v];
+            Rr[v * nm + n] += R(area * w * Blo) * Flo[d][qf * 5 + v];
+            Rt[v * nm + n] -= R(area * w * Bup) * Ftup[d][qf * 5 + v];
+            Rt[v * nm + n] += R(area * w * Blo) * Ftlo[d][qf * 5 + v];
           }
         }
       }
   for (int v = 0; v < 5; ++v)
     for (int n = 0; n < nm; ++n) {
-      Lc[v * nm + n] = Rr[v * nm + n] / R(D.mass[n]);
-      Ltc[v * nm + n] = Rt[v * nm + n] / R(D.mass[n]);
+      Lc[v * nm + n] = Rr[v * nm + n] / R(D.mass[n] * vol);
+      Ltc[v * nm + n] = Rt[v * nm + n] / R(D.mass[n] * vol);
     }
 }
 
@@ -983,25 +1011,23 @@ static void project(const Disc& D, int which, double* q) {
   for (auto& w : wg) w *= 0.5;
 #pragma omp parallel for schedule(static)
   for (int64_t cc = 0; cc < D.ncell; ++cc) {
-    int ii[3];
-    D.ijk(cc, ii[0], ii[1], ii[2]);
     std::vector<double> acc(5 * D.nm, 0.0);
     for (int g = 0; g < ng; ++g)
       for (int b = 0; b < ng; ++b)
         for (int a = 0; a < ng; ++a) {
           double xi[3] = {xg[a], xg[b], xg[g]};
           double x[3];
-          for (int e = 0; e < 3; ++e) x[e] = D.c.lo[e] + (ii[e] + 0.5 + 0.5 * xi[e]) * D.dx[e];
+          D.xphys(cc, xi, x);
           double Q[5];
           exact_state(x, D.c, which, Q);
-          double w = wg[a] * wg[b] * wg[g] * D.vol;
+          double w = wg[a] * wg[b] * wg[g] * D.cvol(cc);
           for (int n = 0; n < D.nm; ++n) {
             double B = D.basis(n, xi);
             for (int v = 0; v < 5; ++v) acc[v * D.nm + n] += w * Q[v] * B;
           }
         }
     for (int v = 0; v < 5; ++v)
-      for (int n = 0; n < D.nm; ++n) q[D.idx(v, n, cc)] = acc[v * D.nm + n] / D.mass[n];
+      for (int n = 0; n < D.nm; ++n) q[D.idx(v, n, cc)] = acc[v * D.nm + n] / (D.mass[n] * D.cvol(cc));
   }
 }
 
@@ -1025,7 +1051,7 @@ static R kinetic_energy(const Disc& D, const R* q) {
       }
       s += R(w) * (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]) / (R(2.0) * Q[0]);
     }
-    part[cc] = s * R(D.vol);
+    part[cc] = s * R(D.cvol(cc));
   }
   R J = R(0.0);
   for (int64_t cc = 0; cc < D.ncell; ++cc) J += part[cc];
@@ -1049,7 +1075,7 @@ static double enstrophy(const Disc& D, const double* q) {
         for (int n = 0; n < nm; ++n) {
           const double c = q[D.idx(v, n, cc)];
           Q[v] += c * D.Bv[(size_t)qi * nm + n];
-          for (int e = 0; e < 3; ++e) G[v][e] += c * D.dBv[((size_t)qi * 3 + e) * nm + n] * 2.0 / D.dx[e];
+          for (int e = 0; e < 3; ++e) G[v][e] += c * D.dBv[((size_t)qi * 3 + e) * nm + n] * 2.0 / D.width(e, cc);
         }
       // dU_j/dx_e = (d(rho U_j)/dx_e - U_j drho/dx_e) / rho
       double dU[3][3];
@@ -1058,7 +1084,7 @@ static double enstrophy(const Disc& D, const double* q) {
       const double ox = dU[2][1] - dU[1][2], oy = dU[0][2] - dU[2][0], oz = dU[1][0] - dU[0][1];
       s += w * 0.5 * (ox * ox + oy * oy + oz * oz);
     }
-    part[cc] = s * D.vol;
+    part[cc] = s * D.cvol(cc);
   }
   double E = 0.0;
   for (int64_t cc = 0; cc < D.ncell; ++cc) E += part[cc];
@@ -1074,14 +1100,12 @@ static double advection_l2_error(const Disc& D, const double* q, double t, int w
   double err = 0.0;
 #pragma omp parallel for reduction(+ : err) schedule(static)
   for (int64_t cc = 0; cc < D.ncell; ++cc) {
-    int ii[3];
-    D.ijk(cc, ii[0], ii[1], ii[2]);
     for (int g = 0; g < nqe; ++g)
       for (int b = 0; b < nqe; ++b)
         for (int a = 0; a < nqe; ++a) {
           double xi[3] = {xg[a], xg[b], xg[g]};
           double x[3];
-          for (int e = 0; e < 3; ++e) x[e] = D.c.lo[e] + (ii[e] + 0.5 + 0.5 * xi[e]) * D.dx[e];
+          D.xphys(cc, xi, x);
           double rho_h = 0.0;
           for (int n = 0; n < D.nm; ++n) rho_h += q[D.idx(0, n, cc)] * D.basis(n, xi);
           double rho_e;
@@ -1090,7 +1114,7 @@ static double advection_l2_error(const Disc& D, const double* q, double t, int w
           else
             rho_e = 1.0 + 0.2 * std::sin(kPi * (x[which - 2] - t));
           double dr = rho_h - rho_e;
-          err += wg[a] * wg[b] * wg[g] * D.vol * dr * dr;
+          err += wg[a] * wg[b] * wg[g] * D.cvol(cc) * dr * dr;
         }
   }
   return std::sqrt(err);

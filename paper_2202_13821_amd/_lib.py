@@ -29,6 +29,7 @@ class dg_hgks_params(ctypes.Structure):
         ("degree", ctypes.c_int32), ("nq", ctypes.c_int32),
         ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("cell_widths", ctypes.c_void_p),
     ]
 
 
@@ -92,7 +93,10 @@ def check(status, ctx=None):
     return status
 
 
-def make_params(shape, lo, hi, degree, nq=0, gamma=1.4, mu=0.0, prandtl=1.0, precision=DG_HGKS_FP64):
+def make_params(shape, lo, hi, degree, nq=0, gamma=1.4, mu=0.0, prandtl=1.0, precision=DG_HGKS_FP64,
+                widths=None):
+    """widths: None, or a contiguous float64 numpy array of nx + ny + nz cell
+    widths that the caller keeps alive until dg_hgks_init has returned."""
     p = dg_hgks_params()
     p.struct_size = ctypes.sizeof(dg_hgks_params)
     p.nx, p.ny, p.nz = (int(s) for s in shape)
@@ -105,4 +109,5 @@ def make_params(shape, lo, hi, degree, nq=0, gamma=1.4, mu=0.0, prandtl=1.0, pre
     p.mu = float(mu)
     p.prandtl = float(prandtl)
     p.precision = int(precision)
+    p.cell_widths = None if widths is None else widths.ctypes.data
     return p

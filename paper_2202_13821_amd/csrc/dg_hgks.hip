@@ -63,6 +63,19 @@ int validate(const dg_hgks_params* p, std::string& why) {
   if (!(p->mu >= 0.0) || !std::isfinite(p->mu)) { why = "mu must be >= 0"; return DG_HGKS_EINVAL; }
   if (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl)) { why = "prandtl must be > 0"; return DG_HGKS_EINVAL; }
   if (p->precision != DG_HGKS_FP64 && p->precision != DG_HGKS_FP32_BULK) { why = "unknown precision"; return DG_HGKS_EINVAL; }
+  if (p->cell_widths) {
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int e = 0, off = 0; e < 3; off += n[e], ++e) {
+      double sum = 0.0;
+      for (int i = 0; i < n[e]; ++i) {
+        const double w = p->cell_widths[off + i];
+        if (!(w > 0.0) || !std::isfinite(w)) { why = "cell_widths must be finite and > 0"; return DG_HGKS_EINVAL; }
+        sum += w;
+      }
+      const double len = p->hi[e] - p->lo[e];
+      if (!(std::fabs(sum - len) <= 1e-10 * len)) { why = "cell_widths must sum to hi - lo on every axis"; return DG_HGKS_EINVAL; }
+    }
+  }
   if (!supported(p->degree, nq)) { why = "(degree, nq) combination not compiled"; return DG_HGKS_EUNSUPPORTED; }
   return DG_HGKS_OK;
 }
@@ -82,6 +95,7 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
     return o;
   };
   L.flag = take(kAlign);
+  L.geo = take((size_t)(p.nx + p.ny + p.nz) * 8);  // cell widths per axis
   L.qs = (Ts == 4) ? take(state * Ts) : 0;
   L.qstar = take(state * Ts);
   L.P = take(state * 8);
@@ -129,18 +143,21 @@ __global__ void clear_flag_kernel(int* f) {
 
 namespace dgrt {
 
-dgk::Geo make_geo(const dg_hgks_params& p) {
+dgk::Geo make_geo(const dg_hgks_ctx* c) {
+  const dg_hgks_params& p = c->p;
   dgk::Geo g{};
   g.nx = p.nx;
   g.ny = p.ny;
   g.nz = p.nz;
   g.ncell = (long long)p.nx * p.ny * p.nz;
-  const int n[3] = {p.nx, p.ny, p.nz};
-  for (int e = 0; e < 3; ++e) {
-    const double dx = (p.hi[e] - p.lo[e]) / n[e];
-    g.two_inv_dx[e] = 2.0 / dx;
-    g.inv_dx[e] = 1.0 / dx;
-  }
+  const double* w = (const double*)(c->ws + c->lay.geo);
+  g.w[0] = w;
+  g.w[1] = w + p.nx;
+  g.w[2] = w + p.nx + p.ny;
+  g.uniform = c->uniform ? 1 : 0;
+  g.two_inv_h[0] = 2.0 / c->widths[0];
+  g.two_inv_h[1] = 2.0 / c->widths[p.nx];
+  g.two_inv_h[2] = 2.0 / c->widths[p.nx + p.ny];
   return g;
 }
 
@@ -173,11 +190,14 @@ int t_end(dg_hgks_ctx* c) {
   DG_HIP(c, hipEventRecord(c->trecs.back().b, c->stream));
   return DG_HGKS_OK;
 }
-int ensure_flag(dg_hgks_ctx* c) {
-  if (c->flag_ready) return DG_HGKS_OK;
+int ensure_ready(dg_hgks_ctx* c) {
+  if (c->ready) return DG_HGKS_OK;
   clear_flag_kernel<<<1, 64, 0, c->stream>>>((int*)(c->ws + c->lay.flag));
   DG_HIP(c, hipGetLastError());
-  c->flag_ready = true;
+  // the source is the context's own host copy, alive until dg_hgks_destroy
+  DG_HIP(c, hipMemcpyAsync(c->ws + c->lay.geo, c->widths.data(), c->widths.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  c->ready = true;
   return DG_HGKS_OK;
 }
 
@@ -185,7 +205,7 @@ int ensure_flag(dg_hgks_ctx* c) {
 
 namespace {
 
-using dgrt::ensure_flag;
+using dgrt::ensure_ready;
 using dgrt::make_geo;
 using dgrt::make_phys;
 using dgrt::t_begin;
@@ -251,6 +271,18 @@ int dg_hgks_init(const dg_hgks_params* p, void* hip_stream, void* workspace, siz
   c->nm = dgk::nmodes(p->degree);
   c->nt = dgk::ntan(p->degree);
   c->mu = p->mu;
+  {
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int e = 0, off = 0; e < 3; off += n[e], ++e)
+      for (int i = 0; i < n[e]; ++i)
+        c->widths.push_back(p->cell_widths ? p->cell_widths[off + i] : (p->hi[e] - p->lo[e]) / n[e]);
+  }
+  c->p.cell_widths = nullptr;  // the caller's array is not kept
+  {
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int e = 0, off = 0; e < 3; off += n[e], ++e)
+      for (int i = 1; i < n[e]; ++i) c->uniform = c->uniform && c->widths[off + i] == c->widths[off];
+  }
   *out = c;
   return DG_HGKS_OK;
 }
@@ -308,7 +340,7 @@ int dg_hgks_set_stream(dg_hgks_ctx* c, void* hip_stream) {
 
 int dg_hgks_check(dg_hgks_ctx* c) {
   if (!c) return DG_HGKS_EINVAL;
-  int rc = ensure_flag(c);
+  int rc = ensure_ready(c);
   if (rc) return rc;
   int h = 0;
   int* f = (int*)(c->ws + c->lay.flag);
@@ -327,7 +359,7 @@ int dg_hgks_point_face_flux(dg_hgks_ctx* c, const double* x, int64_t n, int32_t 
   if (!c) return DG_HGKS_EINVAL;
   if (!x || !F || !Ft || n < 0 || axis < 0 || axis > 2 || !(dt > 0.0)) return fail(c, DG_HGKS_EINVAL, "bad argument");
   if (n == 0) return DG_HGKS_OK;
-  int rc = ensure_flag(c);
+  int rc = ensure_ready(c);
   if (rc) return rc;
   const Phys ph = make_phys(c, dt);
   int* flag = (int*)(c->ws + c->lay.flag);
@@ -343,7 +375,7 @@ int dg_hgks_point_volume_flux(dg_hgks_ctx* c, const double* x, int64_t n, double
   if (!c) return DG_HGKS_EINVAL;
   if (!x || !F || !Ft || n < 0) return fail(c, DG_HGKS_EINVAL, "bad argument");
   if (n == 0) return DG_HGKS_OK;
-  int rc = ensure_flag(c);
+  int rc = ensure_ready(c);
   if (rc) return rc;
   const Phys ph = make_phys(c, 1.0);
   int* flag = (int*)(c->ws + c->lay.flag);
@@ -358,7 +390,9 @@ int dg_hgks_point_volume_flux(dg_hgks_ctx* c, const double* x, int64_t n, double
 int dg_hgks_diagnostics(dg_hgks_ctx* c, const double* q, double* out_host, double* grad_ke) {
   if (!c) return DG_HGKS_EINVAL;
   if (!q || !out_host) return fail(c, DG_HGKS_EINVAL, "NULL pointer");
-  const Geo g = make_geo(c->p);
+  int rc = ensure_ready(c);
+  if (rc) return rc;
+  const Geo g = make_geo(c);
   const long long nb = (g.ncell + kCellThreads - 1) / kCellThreads;
   double* part = (double*)(c->ws + c->lay.diag);
   double* sums = part + 2 * nb;

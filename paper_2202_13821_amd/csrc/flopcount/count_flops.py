@@ -8,8 +8,9 @@ llvm.fmuladd/llvm.fma = 2, fdiv = 1, sqrt/exp/erfc = 1 each (also listed
 apart); vectorisation is disabled, and a vector operation would count once
 per element.  The modal evaluation at the point and the projection onto the modes
 are contractions whose useful flops (non-zero basis entries only) are added
-in closed form (P2, 3 Gauss points per direction, 10 modes, 6 tangential
-modes, 4 modes with a non-zero derivative along each axis).
+in closed form for each compiled (degree, Gauss points) rule (P2: 10 modes,
+6 tangential modes, 4 modes with a non-zero derivative along each axis;
+P3: 20, 10 and 10).
 """
 import json
 import os
@@ -73,32 +74,51 @@ def count(text, fname, bodies=None):
     return dict(c)
 
 
-def main():
-    text = ir()
-    NM, NT, NQ2, NQ3 = 10, 6, 9, 27
-    nd = 4  # P2 modes with a nonzero exponent along a given axis
+def nmodes(k):
+    return (k + 1) * (k + 2) * (k + 3) // 6
+
+
+def totals(counts, k, nq):
+    """Per-point totals of one (degree, Gauss points) rule from the point-flux
+    counts: flux + evaluation of Q and its three derivatives from the modes
+    (both traces at a face point) + projection onto the modes."""
+    NM, NT = nmodes(k), (k + 1) * (k + 2) // 2
+    nd = NM - NT  # modes with a non-zero exponent (non-zero derivative) along a given axis
     # evaluation of Q and the three derivatives at a point: (NM + 3 nd) FMAs per variable
     eval_pt = 5 * (NM + 3 * nd) * 2 + 15
+    d = {}
+    for st in ("s1", "s2"):
+        nf = 2 if st == "s1" else 1
+        face, vol = counts[("face", st)], counts[("vol", st)]
+        # face: two traces, flux, projection on NT tangential modes (per point share)
+        d[f"face_stage{st[1]}"] = 2 * eval_pt + face["flops"] + nf * 5 * NT * 2
+        # volume: one evaluation, flux, projection sum_q w F_d dB_n/dx_d over the
+        # 3 nd non-zero (d, n) entries
+        d[f"volume_stage{st[1]}"] = eval_pt + vol["flops"] + nf * 5 * 3 * nd * 2
+    # per cell and step: 3 faces of nq^2 points and nq^3 volume points, both stages
+    d["per_step_per_cell"] = (3 * nq * nq * (d["face_stage1"] + d["face_stage2"])
+                              + nq ** 3 * (d["volume_stage1"] + d["volume_stage2"]))
+    return d
+
+
+RULES = ((1, 2), (2, 3), (2, 2), (3, 4), (3, 3))
+
+
+def main():
+    text = ir()
     res = {"k": 2, "nq": 3, "counted_from": "optimised host LLVM IR of gks_point.hpp"}
+    rules = {f"p{k}_nq{nq}": {} for k, nq in RULES}
     for T, tag in (("f32", "fp32"), ("f64", "fp64")):
-        d = {}
+        counts = {(kind, st): count(text, f"fc_{kind}_{T}_{st}") for kind in ("face", "vol") for st in ("s1", "s2")}
+        d = totals(counts, 2, 3)
         for st in ("s1", "s2"):
-            nf = 2 if st == "s1" else 1
-            face = count(text, f"fc_face_{T}_{st}")
-            vol = count(text, f"fc_vol_{T}_{st}")
-            # face: two traces, flux, projection on NT tangential modes (per point share)
-            face_total = 2 * eval_pt + face["flops"] + nf * 5 * NT * 2
-            # volume: one evaluation, flux, projection sum_q w F_d dB_n/dx_d over the
-            # 3 nd non-zero (d, n) entries
-            vol_total = eval_pt + vol["flops"] + nf * 5 * 3 * nd * 2
-            d[f"face_stage{st[1]}"] = face_total
-            d[f"volume_stage{st[1]}"] = vol_total
-            d[f"face_point_flux_stage{st[1]}_detail"] = face
-            d[f"volume_point_flux_stage{st[1]}_detail"] = vol
-        res[tag] = d
-    res["per_step_per_cell"] = {tag: 27 * (res[tag]["face_stage1"] + res[tag]["face_stage2"]
-                                           + res[tag]["volume_stage1"] + res[tag]["volume_stage2"])
-                                for tag in ("fp32", "fp64")}
+            d[f"face_point_flux_stage{st[1]}_detail"] = counts[("face", st)]
+            d[f"volume_point_flux_stage{st[1]}_detail"] = counts[("vol", st)]
+        res[tag] = {x: v for x, v in d.items() if x != "per_step_per_cell"}
+        res.setdefault("per_step_per_cell", {})[tag] = d["per_step_per_cell"]
+        for k, nq in RULES:
+            rules[f"p{k}_nq{nq}"][tag] = totals(counts, k, nq)
+    res["rules"] = rules
     path = os.path.join(PKG, "flops.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)

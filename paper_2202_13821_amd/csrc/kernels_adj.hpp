@@ -129,7 +129,10 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
 #pragma unroll
     for (int t = 0; t < NT1; ++t) cn[v][t] = T(0);
   }
-  const double ixd = g.inv_dx[D];
+  // this side's cell: index along each axis (tangential ones shared by the pair)
+  unsigned ci[3];
+  cell_ijk(unsigned(cell), g, ci);
+  const double ixd = 1.0 / g.w[D][ci[D]];
 #pragma unroll
   for (int v = 0; v < 5; ++v)
     static_for<NM>([&](auto nc) {
@@ -174,7 +177,7 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
 #pragma unroll
     for (int t = 0; t < NT1; ++t) cnb[v][t] = T(0);
   }
-  const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
+  const T sn = T(2.0 * ixd), s1 = T(2.0 / g.w[T1][ci[T1]]), s2 = T(2.0 / g.w[T2][ci[T2]]);
   using TB = TanBasisHolder<T, K, NQ>;
   using FT = FaceTabHolder<T, K, NQ>;
   constexpr TanModes<K> tmd{};
@@ -329,7 +332,9 @@ __global__ __launch_bounds__(kCellThreads) void adj_volume_kernel(const T* __res
       cf[v][n] = q[(long long)(v * NM + n) * N + cc];
       sb[v][n] = T(0);
     }
-  const T sc[3] = {T(g.two_inv_dx[0]), T(g.two_inv_dx[1]), T(g.two_inv_dx[2])};
+  unsigned ci[3];
+  cell_ijk(unsigned(cc), g, ci);
+  const T sc[3] = {T(2.0 / g.w[0][ci[0]]), T(2.0 / g.w[1][ci[1]]), T(2.0 / g.w[2][ci[2]])};
   using PB = PointBasisHolder<T, K, NQ>;
   double mub = 0.0;
 #pragma unroll 1

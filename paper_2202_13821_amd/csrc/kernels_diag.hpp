@@ -23,7 +23,11 @@ __global__ __launch_bounds__(kCellThreads) void diag_kernel(const double* __rest
   const long long c = (long long)blockIdx.x * kCellThreads + threadIdx.x;
   const bool act = c < N;
   const long long cc = act ? c : N - 1;
-  const double vol = 1.0 / (g.inv_dx[0] * g.inv_dx[1] * g.inv_dx[2]);
+  unsigned ci[3];
+  cell_ijk(unsigned(cc), g, ci);
+  const double wx = g.w[0][ci[0]], wy = g.w[1][ci[1]], wz = g.w[2][ci[2]];
+  const double vol = wx * wy * wz;
+  const double sx = 2.0 / wx, sy = 2.0 / wy, sz = 2.0 / wz;
   double cf[4][NM], gk[4][NM];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -48,9 +52,9 @@ __global__ __launch_bounds__(kCellThreads) void diag_kernel(const double* __rest
         if constexpr (md.e[n][2] > 0) gz += a * PB::t.dphi[qi][2][n];
       });
       Q[v] = v0;
-      G[v][0] = gx * g.two_inv_dx[0];
-      G[v][1] = gy * g.two_inv_dx[1];
-      G[v][2] = gz * g.two_inv_dx[2];
+      G[v][0] = gx * sx;
+      G[v][1] = gy * sy;
+      G[v][2] = gz * sz;
     }
     const double w = PB::t.w[qi];
     const double ir = 1.0 / Q[0];

@@ -29,11 +29,23 @@ namespace dgk {
 #define DGK_D __device__ __forceinline__
 
 struct Geo {
-  int nx, ny, nz, pad;
+  int nx, ny, nz;
+  int uniform;  // 1: every cell has the widths 2 / two_inv_h[d]
   long long ncell;
-  double two_inv_dx[3];  // 2 / dx_d  (reference -> physical derivative)
-  double inv_dx[3];      // |Gamma_d| / |K| = 1 / dx_d
+  // Separable mesh: w[d][i] is the width of the cells with index i along axis
+  // d (device, FP64).  2 / w maps reference to physical derivatives and
+  // 1 / w = |Gamma_d| / |K| scales a cell's d-face terms.
+  const double* w[3];
+  double two_inv_h[3];  // 2 / width on a uniform mesh (kernel argument, wave-uniform)
 };
+
+// Index of cell c along each axis.
+DGK_D void cell_ijk(unsigned c, const Geo& g, unsigned ijk[3]) {
+  const unsigned nx = unsigned(g.nx), ny = unsigned(g.ny);
+  ijk[0] = c % nx;
+  ijk[1] = (c / nx) % ny;
+  ijk[2] = c / (nx * ny);
+}
 
 // Neighbour of cell c across its upper (+1) or lower (-1) face along axis d,
 // periodic, in 32-bit arithmetic (the cell count is below 2^31).
@@ -162,13 +174,15 @@ DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
 // LDS of one face block (each lane uses only its own column, so no barrier
 // is needed): the upper cell's face-restricted coefficients, and in stage 1
 // the F part of the record accumulators, in stage 2 the lower cell's trace
-// coefficients.  At 2 x 256 lanes per CU this is 80 floats per lane.
+// coefficients; and the cell-width scales of the face.  At 2 x 256 lanes per
+// CU this is 79 floats per lane (of 80).
 template <class T, int K, bool NEED_F, int NTH>
 struct FaceLds {
   static constexpr int NT = ntan(K), NT1 = ntan(K - 1);
   static constexpr int NC = 5 * (NT + NT1);
   T c1[NC][NTH];
   T x[5 * NT][NTH];
+  T st[4][NTH];  // 2 / width along the normal (lower, upper cell) and the two tangents
 };
 
 // Lanes per face block: 256, or 128 where the LDS columns of 256 lanes would
@@ -178,7 +192,7 @@ constexpr int face_threads() {
   return sizeof(FaceLds<T, K, true, kCellThreads>) <= 160 * 1024 ? kCellThreads : kCellThreads / 2;
 }
 
-template <class T, int K, int NQ, bool NEED_F, int D>
+template <class T, int K, int NQ, bool NEED_F, int D, bool UNI>
 DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
                      long long f, FaceLds<T, K, NEED_F, face_threads<T, K>()>& sm) {
   constexpr int NM = nmodes(K), NT = ntan(K), NT1 = ntan(K - 1), NQ2 = NQ * NQ;
@@ -194,6 +208,18 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
   const bool act = f < N;
   const long long fl = act ? f : N - 1;  // lanes past the end recompute the last face, store nothing
   const long long fu = (long long)nb32(unsigned(fl), D, +1, g);
+  // 2 / width along the normal for each side and along the tangents (shared
+  // by the sides): per lane through LDS on a non-uniform mesh (read where
+  // used, to spare registers), wave-uniform kernel arguments on a uniform one
+  if constexpr (!UNI) {
+    unsigned ci[3];
+    cell_ijk(unsigned(fl), g, ci);
+    const unsigned nD = unsigned(D == 0 ? g.nx : (D == 1 ? g.ny : g.nz));
+    sm.st[0][tid] = T(2.0 / g.w[D][ci[D]]);
+    sm.st[1][tid] = T(2.0 / g.w[D][ci[D] + 1 == nD ? 0 : ci[D] + 1]);
+    sm.st[2][tid] = T(2.0 / g.w[T1][ci[T1]]);
+    sm.st[3][tid] = T(2.0 / g.w[T2][ci[T2]]);
+  }
 
   // The traces on this face depend on a cell's modes only through their
   // values at xi_D = +-1: per side s and variable, the tangential-mode
@@ -250,7 +276,6 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       acc[r][m] = T(0);
       if constexpr (NEED_F) sm.x[r * NT + m][tid] = T(0);
     }
-  const T sn = T(g.two_inv_dx[D]), s1 = T(g.two_inv_dx[T1]), s2 = T(g.two_inv_dx[T2]);
   using TB = TanBasisHolder<T, K, NQ>;
   constexpr TanModes<K> tmd{};
   int bad = 0;
@@ -289,9 +314,15 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
           }
         });
         qs[vl] = v0;
-        dqs[0][vl] = vn * sn;
-        dqs[1][vl] = v1 * s1;
-        dqs[2][vl] = v2 * s2;
+        if constexpr (UNI) {
+          dqs[0][vl] = vn * T(g.two_inv_h[D]);
+          dqs[1][vl] = v1 * T(g.two_inv_h[T1]);
+          dqs[2][vl] = v2 * T(g.two_inv_h[T2]);
+        } else {
+          dqs[0][vl] = vn * sm.st[side][tid];
+          dqs[1][vl] = v1 * sm.st[2][tid];
+          dqs[2][vl] = v2 * sm.st[3][tid];
+        }
       }
       face_side(ph, qs, dqs, fa, bad, T(side == 0 ? 1 : -1));
     });
@@ -322,7 +353,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
 }
 
 // Minimum waves per SIMD requested for the face kernel (register budget):
-// two for FP32 up to P2 (the LDS columns then take 80 floats per lane), one
+// two for FP32 up to P2 (the LDS columns then take 79 floats per lane), one
 // otherwise.
 template <class T, int K>
 struct FaceWaves {
@@ -332,7 +363,7 @@ struct FaceWaves {
 // Grid: 3 nb blocks of face_threads<T, K>() lanes, nb = ceil(N / lanes);
 // the logical block (after the XCD reordering) picks the normal axis and the
 // range of faces.
-template <class T, int K, int NQ, bool NEED_F>
+template <class T, int K, int NQ, bool NEED_F, bool UNI>
 __global__ __launch_bounds__((face_threads<T, K>()), (FaceWaves<T, K>::value)) void face_kernel(
     const T* __restrict__ q, T* __restrict__ rec, Geo g, Phys ph, int* flag) {
   constexpr int FT = face_threads<T, K>();
@@ -342,9 +373,9 @@ __global__ __launch_bounds__((face_threads<T, K>()), (FaceWaves<T, K>::value)) v
   const long long f = (long long)(lb - d * nb) * FT + threadIdx.x;
   __shared__ FaceLds<T, K, NEED_F, FT> sm;
   switch (d) {
-    case 0: face_lane<T, K, NQ, NEED_F, 0>(q, rec, g, ph, flag, f, sm); break;
-    case 1: face_lane<T, K, NQ, NEED_F, 1>(q, rec, g, ph, flag, f, sm); break;
-    default: face_lane<T, K, NQ, NEED_F, 2>(q, rec, g, ph, flag, f, sm); break;
+    case 0: face_lane<T, K, NQ, NEED_F, 0, UNI>(q, rec, g, ph, flag, f, sm); break;
+    case 1: face_lane<T, K, NQ, NEED_F, 1, UNI>(q, rec, g, ph, flag, f, sm); break;
+    default: face_lane<T, K, NQ, NEED_F, 2, UNI>(q, rec, g, ph, flag, f, sm); break;
   }
 }
 
@@ -412,7 +443,7 @@ struct PointBasisHolder {
   static constexpr PointBasis<T, K, NQ> t{};
 };
 
-template <class T, int K, int NQ, int MODE>
+template <class T, int K, int NQ, int MODE, bool UNI>
 __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,
                                                              Geo g, Phys ph, VolOut<T> out, int* flag) {
   constexpr int NM = nmodes(K), NT = ntan(K), NQ3 = NQ * NQ * NQ;
@@ -425,7 +456,17 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
   const bool act = c < N;
   const long long cc = act ? c : N - 1;  // lanes past the end recompute the last cell, store nothing
 
-  // acc[f][v][n] = sum_q w_q sum_d F^f_d[v](x_q) (2/dx_d) dB_n/dxi_d (x_q), f = F | Ft
+  // 2 / width of this cell per axis: on a non-uniform mesh kept in LDS (read
+  // where used, to spare registers), on a uniform one the kernel arguments
+  __shared__ T sc[3][UNI ? 1 : kCellThreads];
+  if constexpr (!UNI) {
+    unsigned ci[3];
+    cell_ijk(unsigned(cc), g, ci);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sc[d][threadIdx.x] = T(2.0 / g.w[d][ci[d]]);
+  }
+  auto scale = [&](int d) -> T { return UNI ? T(g.two_inv_h[d]) : sc[d][UNI ? 0 : threadIdx.x]; };
+  // acc[f][v][n] = sum_q w_q sum_d F^f_d[v](x_q) (2/w_d) dB_n/dxi_d (x_q), f = F | Ft
   T acc[NF][5][NM];
 #pragma unroll
   for (int f = 0; f < NF; ++f)
@@ -442,7 +483,7 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
   const long long ntile = (N + 63) >> 6;
   static_for<3>([&](auto dc) {
     constexpr int d = decltype(dc)::value;
-    const T ix = T(g.inv_dx[d]);
+    const T ix = T(0.5) * scale(d);  // 1 / width = |Gamma_d| / |K|
     const T* pu = rec + rec_index(d, cc, 0, RECN, ntile);
     const T* pl = rec + rec_index(d, (long long)nb32(unsigned(cc), d, -1, g), 0, RECN, ntile);
     static_for<NF>([&](auto fc) {
@@ -470,17 +511,18 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
 #pragma unroll
     for (int n = 0; n < NM; ++n) cf[v][n] = q[(long long)(v * NM + n) * N + cc];
 
-  const T sc[3] = {T(g.two_inv_dx[0]), T(g.two_inv_dx[1]), T(g.two_inv_dx[2])};
   using PB = PointBasisHolder<T, K, NQ>;
   int bad = 0;
 #pragma unroll 1
   for (int qi = 0; qi < NQ3; ++qi) {
-    // physical-space derivative of the basis at this point (uniform)
+    // keeps the width scales in LDS: no load moves across this point
+    __asm__ __volatile__("" ::: "memory");
+    // physical-space derivative of the basis at this point (this cell's widths)
     T ds[3][NM];
     static_for<NM>([&](auto nc) {
       constexpr int n = decltype(nc)::value;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ds[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] * sc[d] : T(0);
+      for (int d = 0; d < 3; ++d) ds[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] * scale(d) : T(0);
     });
     T Q[5], dQ[3][5];
 #pragma unroll

@@ -36,25 +36,31 @@ int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g,
   const unsigned nvb = (unsigned)((N + kCellThreads - 1) / kCellThreads);
   constexpr int FT = face_threads<T, K>();
   const unsigned nfb = (unsigned)((N + FT - 1) / FT);
-  if constexpr (MODE == 1) {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
-  } else {
-    DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
-  }
-  DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE><<<dim3(nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, o, flag)));
-  return DG_HGKS_OK;
+  // uniform meshes take the cell widths from the kernel arguments
+  auto run = [&](auto uc) {
+    constexpr bool UNI = decltype(uc)::value;
+    if constexpr (MODE == 1) {
+      DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, false, UNI><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
+    } else {
+      DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true, UNI><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
+    }
+    DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE, UNI><<<dim3(nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, o,
+                                                                                                   flag)));
+    return DG_HGKS_OK;
+  };
+  return g.uniform ? run(std::true_type{}) : run(std::false_type{});
 }
 
 template <class T, int K, int NQ>
 int run_step(dg_hgks_ctx* c, double* q, double dt, int nsteps, double* ckpt, int stride) {
-  const Geo g = make_geo(c->p);
+  const Geo g = make_geo(c);
   const Phys ph = make_phys(c, dt);
   const long long n = 5LL * c->nm * g.ncell;
   constexpr bool bulk = sizeof(T) == 4;
   T* qs = bulk ? (T*)(c->ws + c->lay.qs) : nullptr;
   T* qstar = (T*)(c->ws + c->lay.qstar);
   double* P = (double*)(c->ws + c->lay.P);
-  int rc = ensure_flag(c);
+  int rc = ensure_ready(c);
   if (rc) return rc;
   if (bulk && nsteps > 0) {
     rc = launch_convert<T>(c, q, qs, n);
@@ -85,10 +91,10 @@ int run_step(dg_hgks_ctx* c, double* q, double dt, int nsteps, double* ckpt, int
 
 template <class T, int K, int NQ>
 int run_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* Lt) {
-  const Geo g = make_geo(c->p);
+  const Geo g = make_geo(c);
   const Phys ph = make_phys(c, dt);
   const long long n = 5LL * c->nm * g.ncell;
-  int rc = ensure_flag(c);
+  int rc = ensure_ready(c);
   if (rc) return rc;
   const T* qin;
   if constexpr (sizeof(T) == 4) {
@@ -130,7 +136,7 @@ int launch_adj_stage(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, doubl
 template <class T, int K, int NQ>
 int run_adjoint(dg_hgks_ctx* c, const double* ckpt, int stride, double dt, int nsteps, const double* qN_bar,
                 double* q0_bar, double* mu_bar_host) {
-  const Geo g = make_geo(c->p);
+  const Geo g = make_geo(c);
   const Phys ph = make_phys(c, dt);
   const long long n = 5LL * c->nm * g.ncell;
   constexpr bool bulk = sizeof(T) == 4;
@@ -143,7 +149,7 @@ int run_adjoint(dg_hgks_ctx* c, const double* ckpt, int stride, double dt, int n
   double* mu = (double*)(c->ws + c->lay.adj_mu);
   double* mu_out = (double*)(c->ws + c->lay.adj_tmp);
   const long long nslots = (long long)adj_mu_slots((size_t)g.ncell);
-  int rc = ensure_flag(c);
+  int rc = ensure_ready(c);
   if (rc) return rc;
   DG_HIP(c, hipMemcpyAsync(qbar, qN_bar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   DG_LAUNCH(c, 2, (zero_kernel<<<dim3(256), 256, 0, c->stream>>>(mu, nslots)));

@@ -15,7 +15,7 @@ namespace dgrt {
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-  size_t flag = 0, qs = 0, qstar = 0, P = 0, rec = 0, diag = 0;
+  size_t flag = 0, geo = 0, qs = 0, qstar = 0, P = 0, rec = 0, diag = 0;
   size_t adj_states = 0, adj_stars = 0, adj_qbar = 0, adj_qsbar = 0, adj_Lbar = 0, adj_Ltbar = 0, adj_frec = 0,
          adj_mu = 0, adj_tmp = 0;
   size_t total = 0;
@@ -38,7 +38,9 @@ struct dg_hgks_ctx {
   long long ncell = 0;
   int nm = 0, nt = 0;
   double mu = 0.0;
-  bool flag_ready = false;
+  bool ready = false;          // flag cleared and cell widths uploaded
+  std::vector<double> widths;  // nx + ny + nz cell widths (x, y, z)
+  bool uniform = true;         // every axis has equal widths
   std::string err;
   bool timing = false;
   std::vector<dgrt::TimingRec> trecs;
@@ -50,13 +52,14 @@ namespace dgrt {
 
 // Record msg as the context's (or, for c == nullptr, the thread's init) error.
 int fail(dg_hgks_ctx* c, int code, const std::string& msg);
-dgk::Geo make_geo(const dg_hgks_params& p);
+dgk::Geo make_geo(const dg_hgks_ctx* c);
 dgk::Phys make_phys(const dg_hgks_ctx* c, double dt);
 // HIP events around one launch of timing class cls (when timing is on).
 int t_begin(dg_hgks_ctx* c, int cls);
 int t_end(dg_hgks_ctx* c);
-// Clear the non-physical-state flag once per context (a kernel, not a memset).
-int ensure_flag(dg_hgks_ctx* c);
+// Once per context, on its stream: clear the non-physical-state flag (a
+// kernel, not a memset) and upload the cell widths to the workspace.
+int ensure_ready(dg_hgks_ctx* c);
 
 // Entry points of one compiled configuration (launch.hpp).
 template <class T, int K, int NQ>

@@ -7,6 +7,7 @@ runs in libdg_hgks.so.
 import ctypes
 import math
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -26,7 +27,10 @@ class Solver:
     """
 
     def __init__(self, shape, lo, hi, degree, nq=0, gamma=1.4, mu=0.0, prandtl=1.0, precision="fp64",
-                 device="cuda", max_stride=0):
+                 device="cuda", max_stride=0, widths=None):
+        """widths: optional separable mesh, the nx + ny + nz cell widths (x,
+        then y, then z), each axis summing to hi - lo (see problems.mapped_widths);
+        None for uniform cells."""
         self.lib = _lib.load()
         self.shape = tuple(int(s) for s in shape)
         self.lo, self.hi = tuple(lo), tuple(hi)
@@ -36,7 +40,9 @@ class Solver:
         self._mu = float(mu)
         self.precision = precision
         self.device = torch.device(device)
-        self.params = _lib.make_params(self.shape, lo, hi, degree, nq, gamma, mu, prandtl, PRECISIONS[precision])
+        self.widths = None if widths is None else np.ascontiguousarray(widths, dtype=np.float64).ravel()
+        self.params = _lib.make_params(self.shape, lo, hi, degree, nq, gamma, mu, prandtl, PRECISIONS[precision],
+                                       self.widths)
         nbytes = self.lib.dg_hgks_workspace_bytes(ctypes.byref(self.params), int(max_stride))
         if nbytes == 0:
             raise _lib.DGHGKSError(_lib.DG_HGKS_EINVAL, "invalid parameters")

@@ -35,10 +35,10 @@ def rel_max(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def pair(shape, k, lo, hi, nq=0, mu=0.0, pr=1.0, gamma=1.4, precision="fp64", max_stride=0):
+def pair(shape, k, lo, hi, nq=0, mu=0.0, pr=1.0, gamma=1.4, precision="fp64", max_stride=0, widths=None):
     s = Solver(shape, lo, hi, k, nq=nq, gamma=gamma, mu=mu, prandtl=pr, precision=precision, device="cuda:0",
-               max_stride=max_stride)
-    c = O.make_cfg(shape, k, nq=nq or k + 1, lo=lo, hi=hi, gamma=gamma, mu=mu, prandtl=pr)
+               max_stride=max_stride, widths=widths)
+    c = O.make_cfg(shape, k, nq=nq or k + 1, lo=lo, hi=hi, gamma=gamma, mu=mu, prandtl=pr, widths=widths)
     return s, c
 
 

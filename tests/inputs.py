@@ -52,3 +52,24 @@ def random_field(rng, shape, nmodes, amp=0.02, low_mach=False):
 
 def random_direction(rng, like):
     return rng.normal(0.0, 1.0, size=like.shape)
+
+
+def mapped_widths(n, lo=0.0, hi=2.0, amp=0.05):
+    """Cell widths along one axis of the Section 5.1 non-uniform mesh: nodes
+    xi_i = lo + i (hi - lo) / n mapped by x = xi + amp (hi - lo) / 2
+    sin(2 pi (xi - lo) / (hi - lo)), i.e. x = xi + 0.05 sin(pi xi) on [0, 2]."""
+    L = hi - lo
+    xi = lo + np.arange(n + 1) * (L / n)
+    x = xi + amp * L / 2.0 * np.sin(2.0 * np.pi * (xi - lo) / L)
+    x[0], x[-1] = lo, hi
+    return np.diff(x)
+
+
+def random_widths(rng, shape, lo, hi, spread=0.4):
+    """nx + ny + nz random cell widths, uniform in [1 - spread, 1 + spread]
+    times the mean width, each axis summing to hi - lo."""
+    out = []
+    for e, n in enumerate(shape):
+        w = rng.uniform(1.0 - spread, 1.0 + spread, n)
+        out.append(w * (hi[e] - lo[e]) / w.sum())
+    return np.concatenate(out)

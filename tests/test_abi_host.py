@@ -4,6 +4,7 @@ the device (dg_hgks_init launches nothing and allocates nothing)."""
 import ctypes
 import re
 
+import numpy as np
 import pytest
 
 from paper_2202_13821_amd import _lib
@@ -23,7 +24,7 @@ def _params(**kw):
                 precision=_lib.DG_HGKS_FP64)
     base.update(kw)
     return _lib.make_params(base["shape"], base["lo"], base["hi"], base["degree"], base["nq"], base["gamma"],
-                            base["mu"], base["prandtl"], base["precision"])
+                            base["mu"], base["prandtl"], base["precision"], base.get("widths"))
 
 
 def test_every_declared_symbol_is_exported():
@@ -36,7 +37,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_params_struct_size():
-    assert ctypes.sizeof(_lib.dg_hgks_params) == 104
+    assert ctypes.sizeof(_lib.dg_hgks_params) == 112
 
 
 def test_nmodes():
@@ -128,3 +129,21 @@ def test_strerror():
     for code in (0, -1, -2, -3, -4, -5):
         assert L.dg_hgks_strerror(code)
     assert L.dg_hgks_strerror(123) == b"unknown status"
+
+
+def test_init_validates_cell_widths():
+    """Separable meshes: every width finite and > 0, each axis summing to
+    hi - lo; the array is copied, so it may be freed after init."""
+    shape, hi = (3, 2, 2), (1.5, 1.0, 2.0)
+    good = np.array([0.4, 0.6, 0.5, 0.3, 0.7, 1.5, 0.5])
+    ctx = ctypes.c_void_p()
+    for w, rc in ((good, 0), (np.array([0.4, 0.6, 0.5, 0.3, 0.7, 1.4, 0.5]), _lib.DG_HGKS_EINVAL),
+                  (np.array([0.4, 0.6, 0.5, -0.3, 1.3, 1.5, 0.5]), _lib.DG_HGKS_EINVAL),
+                  (np.array([0.4, 0.6, 0.5, np.nan, 0.7, 1.5, 0.5]), _lib.DG_HGKS_EINVAL)):
+        p = _params(shape=shape, hi=hi, widths=np.ascontiguousarray(w))
+        need = L.dg_hgks_workspace_bytes(ctypes.byref(p), 0)
+        assert (need > 0) == (rc == 0)
+        got = L.dg_hgks_init(ctypes.byref(p), None, ctypes.c_void_p(1 << 20), 1 << 30, ctypes.byref(ctx))
+        assert got == rc, (w, got)
+        if rc == 0:
+            assert L.dg_hgks_destroy(ctx) == 0

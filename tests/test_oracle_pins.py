@@ -493,3 +493,103 @@ def test_dual_step_and_energy_vs_central_differences(orc):
         Jp = orc.kinetic_energy(c, orc.step(mk(mu + h * tmu), q + h * vv, dt, n))
         Jm = orc.kinetic_energy(c, orc.step(mk(mu - h * tmu), q - h * vv, dt, n))
         assert abs(dJ - (Jp - Jm) / (2 * h)) <= 1e-8 * abs(dJ)
+
+
+# ---------------------------------------------------------------------------
+# separable non-uniform meshes (Section 5.1 mapped meshes)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_nonuniform_free_stream_and_conservation(orc, k):
+    rng = np.random.default_rng(30 + k)
+    shape, lo, hi = (5, 3, 4), (0.0, 0.0, 0.0), (1.0, 2.0, 3.0)
+    w = IN.random_widths(rng, shape, lo, hi)
+    c = orc.make_cfg(shape, k, lo=lo, hi=hi, mu=0.01, prandtl=0.72, widths=w)
+    Q = [1.2, 0.3, -0.4, 0.5, 3.0]
+    q = _uniform(orc, c, Q)
+    L, Lt = orc.residual(c, q, 1e-2)
+    tol = 1e-15 * max(abs(v) for v in Q) * orc.nmodes(k) * (2 * k + 1) / w.min()
+    assert np.abs(L).max() < tol and np.abs(Lt).max() < tol
+    # conservation: the integral of each variable is sum_K |K| Q_0(K)
+    q = IN.random_field(rng, shape, orc.nmodes(k), amp=0.05)
+    nx, ny = shape[0], shape[1]
+    vol = w[nx + ny:][:, None, None] * w[nx:nx + ny][None, :, None] * w[:nx][None, None, :]
+    tot0 = (q[:, 0] * vol).sum(axis=(1, 2, 3))
+    q2 = orc.step(c, q, 2e-3, 3)
+    tot1 = (q2[:, 0] * vol).sum(axis=(1, 2, 3))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(tot0).max())
+
+
+def test_nonuniform_equal_widths_reproduce_uniform_mesh(orc):
+    rng = np.random.default_rng(41)
+    shape, lo, hi = (4, 3, 5), (0.0, -1.0, 0.5), (1.0, 1.0, 2.0)
+    w = np.concatenate([np.full(n, (hi[e] - lo[e]) / n) for e, n in enumerate(shape)])
+    q = IN.random_field(rng, shape, 10, amp=0.05)
+    a = orc.residual(orc.make_cfg(shape, 2, lo=lo, hi=hi, mu=0.01, prandtl=0.72), q, 1e-2)
+    b = orc.residual(orc.make_cfg(shape, 2, lo=lo, hi=hi, mu=0.01, prandtl=0.72, widths=w), q, 1e-2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_nonuniform_transverse_widths_do_not_change_a_one_dimensional_flow(orc):
+    """A field that varies along x only has equal states on both faces of
+    every y and z face pair, whose terms then cancel whatever the y and z
+    widths: the residual is that of the 1-D grid.  A width taken from the
+    wrong axis (normal derivative, face area, mass matrix) breaks this."""
+    rng = np.random.default_rng(42)
+    nx, lo, hi = 6, (0.0, 0.0, 0.0), (2.0, 1.0, 1.5)
+    wx = IN.random_widths(rng, (nx,), lo[:1], hi[:1])
+    q1 = IN.random_field(rng, (nx, 1, 1), 10, amp=0.05)
+    # keep only modes constant in y and z (e_y = e_z = 0): modes 0, 1 (x), 4 (x^2) of P2
+    md = orc.modes(2)
+    keep = [n for n in range(10) if md[n][1] == 0 and md[n][2] == 0]
+    q1[:, [n for n in range(10) if n not in keep]] = 0.0
+    c1 = orc.make_cfg((nx, 1, 1), 2, lo=lo, hi=hi, mu=0.01, prandtl=0.72,
+                      widths=np.concatenate([wx, [1.0], [1.5]]))
+    L1, Lt1 = orc.residual(c1, q1, 1e-2)
+    shape = (nx, 3, 4)
+    w = np.concatenate([wx, IN.random_widths(rng, (3, 4), lo[1:], hi[1:])])
+    c3 = orc.make_cfg(shape, 2, lo=lo, hi=hi, mu=0.01, prandtl=0.72, widths=w)
+    q3 = np.broadcast_to(q1, (5, 10, 4, 3, nx)).copy()
+    L3, Lt3 = orc.residual(c3, q3, 1e-2)
+    for L, ref in ((L3, L1), (Lt3, Lt1)):
+        scale = np.abs(ref).max()
+        assert np.abs(L - ref).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("k,axis", [(2, 0), (3, 1)])
+def test_nonuniform_convergence_order_1d(orc, k, axis):
+    """Section 5.1 mapped mesh x = xi + 0.05 sin(pi xi) along the flow: order k + 1."""
+    e = []
+    for N in (8, 16, 32):
+        shape = [1, 1, 1]
+        shape[axis] = N
+        ws = [np.array([2.0])] * 3
+        ws[axis] = IN.mapped_widths(N)
+        c = orc.make_cfg(shape, k, lo=(0, 0, 0), hi=(2, 2, 2), widths=np.concatenate(ws))
+        prob = "advection_" + "xyz"[axis]
+        q = orc.project(c, prob)
+        amax = 1.0 + np.sqrt(GAMMA / 0.8)
+        n = int(np.ceil(0.5 / (0.1 * ws[axis].min() / amax)))
+        q = orc.step(c, q, 0.5 / n, n)
+        e.append(orc.advection_error(c, q, 0.5, prob))
+    orders = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all(np.abs(orders - (k + 1)) < 0.3), orders
+
+
+def test_mapped_mesh_error_ratio_matches_paper_tables(orc):
+    """3-D advection, P2 with the paper's 2 Gauss points per direction, 8^3:
+    the L2 error on the mapped mesh over the error on the uniform mesh.  The
+    paper's tables of the 3-D P2 accuracy test give 1.6035e-2 (mapped) and
+    1.4834e-2 (uniform; printed as 1.4834e-3, read as e-2 since the printed
+    order 3.6965 to the 16^3 value 1.1441e-3 requires it): a ratio of 1.081.
+    The final time is not stated with the tables, so the ratio (insensitive
+    to it) is compared, within 3%."""
+    errs = []
+    for w in (None, np.tile(IN.mapped_widths(8), 3)):
+        c = orc.make_cfg((8, 8, 8), 2, nq=2, lo=(0, 0, 0), hi=(2, 2, 2), widths=w)
+        q = orc.project(c, "advection")
+        dxm = 0.25 if w is None else w.min()
+        n = int(np.ceil(0.5 / (0.1 * dxm / (1.0 + np.sqrt(GAMMA / 0.8)))))
+        q = orc.step(c, q, 0.5 / n, n)
+        errs.append(orc.advection_error(c, q, 0.5))
+    ratio = errs[1] / errs[0]
+    assert abs(ratio / (1.6035e-2 / 1.4834e-2) - 1.0) < 0.03, ratio

@@ -27,7 +27,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 def ir():
     out = os.path.join("/tmp", "dg_flopcount.ll")
     subprocess.run([HIPCC, "--cuda-host-only", "-O2", "-std=c++17", "-ffp-contract=on", "-fno-vectorize",
-                    "-fno-slp-vectorize", "-funroll-loops", "-mllvm", "-unroll-threshold=1000000",
+                    "-fno-slp-vectorize", "-DDGK_FLOPCOUNT", "-funroll-loops", "-mllvm", "-unroll-threshold=1000000",
                     "-mllvm", "-unroll-max-count=4096", "-S", "-emit-llvm",
                     "-I", os.path.dirname(HERE), "-o", out, os.path.join(HERE, "flopcount.hip")], check=True)
     return open(out).read()

@@ -145,6 +145,40 @@ struct Solver5 {
   }
 };
 
+// exp(-x) for x >= 0 in FP64 from a table ec of 15 constants that the caller
+// keeps where uniform loads are cheap (LDS in the face kernel): Cody-Waite
+// reduction x = k ln 2 + r with ln 2 split into a high part with 21 trailing
+// zero bits (k ln2_hi is exact for k < 2^21) and a low part, |r| <= ln2 / 2,
+// then exp(-r) by its Taylor polynomial of degree 13 (truncation below 5e-18
+// relative) and the exact scaling by 2^-k.  ec = (log2 e, ln2_hi, ln2_lo,
+// 1/2!, ..., 1/13!).
+struct ExpTab {
+  double c[15];
+};
+template <int = 0>
+struct ExpTabHolder {
+  static constexpr ExpTab t{{0x1.71547652b82fep+0, 0x1.62e42fee00000p-1, 0x1.a39ef35793c76p-33, 1.0 / 2.0,
+                             1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0,
+                             1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
+                             1.0 / 6227020800.0}};
+};
+DGK_HD double exp_neg_tab(double x, const double* ec) {
+#ifdef DGK_FLOPCOUNT
+  (void)ec;
+  return exp(-x);  // counted as one transcendental, like the other exp calls
+#else
+  x = fmin(x, 800.0);  // exp(-800) already underflows to 0
+  const double k = rint(x * ec[0]);
+  const double s = -fma(-k, ec[2], fma(-k, ec[1], x));  // -(x - k ln 2)
+  double p = ec[14];
+#pragma unroll
+  for (int i = 13; i >= 3; --i) p = fma(p, s, ec[i]);
+  p = fma(p, s, 1.0);
+  p = fma(p, s, 1.0);
+  return ldexp(p, -int(k));
+#endif
+}
+
 // Time-integral coefficients (FP64).  With e(t) = exp(-t/tau), the time
 // factors of Eq. (flux) integrate over [0, delta] to
 //   c1 = delta - tau (1 - e),          c2 = 2 tau^2 - tau delta - tau (2 tau + delta) e,
@@ -162,9 +196,11 @@ struct Solver5 {
 // so that the finish can combine differences of the equilibrium and
 // non-equilibrium moments.
 // tau = 0 is the inviscid limit (e = 0): F = m1, Ft = m3.
-// x_half = dt / (2 tau) (0 when tau = 0), inv_dt = 1 / dt.
-DGK_HD void time_coefficients(double tau, double x_half, double dt, double inv_dt, double alpha[6], double beta[6]) {
-  const double e = tau > 0.0 ? exp(-x_half) : 0.0;
+// x_half = dt / (2 tau) (0 when tau = 0), inv_dt = 1 / dt; ec: the table of
+// exp_neg_tab.
+DGK_HD void time_coefficients(double tau, double x_half, double dt, double inv_dt, double alpha[6], double beta[6],
+                              const double* ec) {
+  const double e = tau > 0.0 ? exp_neg_tab(x_half, ec) : 0.0;
   const double x = tau * inv_dt;
   const double om = 1.0 - e;
   const double A = om * (3.0 - e), B = om * om;
@@ -457,8 +493,9 @@ DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>
   sym_mv_acc(H, a[2], r, acc.m5);
 }
 
+// ec: the constants of exp_neg_tab (LDS in the face kernel).
 template <class T, bool NEED_F>
-DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], int& bad) {
+DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], int& bad, const double* ec) {
   const T K = T(ph.K), gm1 = T(ph.gm1);
   const Prim<T> s0 = primitive(acc.Q0, gm1);
   bad |= int(unphysical(s0));
@@ -474,7 +511,7 @@ DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], 
 
   const double tau = ph.mu / double(s0.p);
   double al[6], be[6];
-  time_coefficients(tau, ph.half_dt_over_mu * double(s0.p), ph.dt, ph.inv_dt, al, be);
+  time_coefficients(tau, ph.half_dt_over_mu * double(s0.p), ph.dt, ph.inv_dt, al, be, ec);
   // beta_3 = -beta_0, beta_4 = -beta_1, alpha_3 = 1 - alpha_0, alpha_4 = -tau - alpha_1:
   //   Ft = beta_0 (m1 - m4) + beta_1 (m2 - m5) + beta_2 m3 + beta_5 m6
   //   F  = m4 + alpha_0 (m1 - m4) + alpha_1 (m2 - m5) - tau m5 + alpha_2 m3 + alpha_5 m6
@@ -503,7 +540,7 @@ DGK_HD void face_flux_local(const Phys& ph, const T qL[5], const T dqL[3][5], co
   face_acc_zero(acc);
   face_side(ph, qL, dqL, acc, bad, T(1));
   face_side(ph, qR, dqR, acc, bad, T(-1));
-  face_finish<T, NEED_F>(ph, acc, F, Ft, bad);
+  face_finish<T, NEED_F>(ph, acc, F, Ft, bad, ExpTabHolder<>::t.c);
 }
 
 // --------------------------------------------------------------------------

@@ -317,7 +317,7 @@ DGK_HD void ns_moment_bwd(const Prim<T>& s, const Grad<T>& g, T two_k3, T cp, co
 // Given the cotangents of alpha and beta, add those of tau and x_half.
 DGK_HD void time_coefficients_bwd(double tau, double x_half, double dt, double inv_dt, const double alb[6],
                                   const double beb[6], double& taub, double& xb) {
-  const double e2 = tau > 0.0 ? exp(-x_half) : 0.0;
+  const double e2 = tau > 0.0 ? exp_neg_tab(x_half, ExpTabHolder<>::t.c) : 0.0;
   const double e1 = e2 * e2;
   const double idt = inv_dt, idt2 = 4.0 * idt * idt;
   const double dl[2] = {dt, 0.5 * dt};
@@ -702,7 +702,7 @@ DGK_HD void face_finish_vjp(const Phys& ph, const FaceAcc<T>& acc, const T Fb[5]
   const double ip0 = 1.0 / p0;
   const double tau = ph.mu * ip0, xh = ph.half_dt_over_mu * p0;
   double al[6], be[6];
-  time_coefficients(tau, xh, ph.dt, ph.inv_dt, al, be);
+  time_coefficients(tau, xh, ph.dt, ph.inv_dt, al, be, ExpTabHolder<>::t.c);
   const T* mm[6] = {m1, m2, m3, acc.m4, acc.m5, acc.m6};
   double alb[6], beb[6];
   T mb[6][5];

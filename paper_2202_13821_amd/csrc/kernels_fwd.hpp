@@ -194,7 +194,7 @@ constexpr int face_threads() {
 
 template <class T, int K, int NQ, bool NEED_F, int D, bool UNI>
 DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g, const Phys& ph, int* flag,
-                     long long f, FaceLds<T, K, NEED_F, face_threads<T, K>()>& sm) {
+                     long long f, FaceLds<T, K, NEED_F, face_threads<T, K>()>& sm, const double* ec) {
   constexpr int NM = nmodes(K), NT = ntan(K), NT1 = ntan(K - 1), NQ2 = NQ * NQ;
   constexpr int NF = NEED_F ? 2 : 1;
   constexpr int RECN = 5 * NF * NT;
@@ -327,7 +327,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       face_side(ph, qs, dqs, fa, bad, T(side == 0 ? 1 : -1));
     });
     T F[5], Ft[5];
-    face_finish<T, NEED_F>(ph, fa, F, Ft, bad);
+    face_finish<T, NEED_F>(ph, fa, F, Ft, bad, ec);
     // record component order: (F|Ft, global variable, tangential mode)
     static_for<NT>([&](auto mc) {
       constexpr int m = decltype(mc)::value;
@@ -372,10 +372,15 @@ __global__ __launch_bounds__((face_threads<T, K>()), (FaceWaves<T, K>::value)) v
   const unsigned d = lb / nb;
   const long long f = (long long)(lb - d * nb) * FT + threadIdx.x;
   __shared__ FaceLds<T, K, NEED_F, FT> sm;
+  // the constants of the FP64 exp of the time coefficients: read from LDS at
+  // every point rather than kept in (and spilled from) registers
+  __shared__ double ec[15];
+  if (threadIdx.x < 15) ec[threadIdx.x] = ExpTabHolder<>::t.c[threadIdx.x];
+  __syncthreads();
   switch (d) {
-    case 0: face_lane<T, K, NQ, NEED_F, 0, UNI>(q, rec, g, ph, flag, f, sm); break;
-    case 1: face_lane<T, K, NQ, NEED_F, 1, UNI>(q, rec, g, ph, flag, f, sm); break;
-    default: face_lane<T, K, NQ, NEED_F, 2, UNI>(q, rec, g, ph, flag, f, sm); break;
+    case 0: face_lane<T, K, NQ, NEED_F, 0, UNI>(q, rec, g, ph, flag, f, sm, ec); break;
+    case 1: face_lane<T, K, NQ, NEED_F, 1, UNI>(q, rec, g, ph, flag, f, sm, ec); break;
+    default: face_lane<T, K, NQ, NEED_F, 2, UNI>(q, rec, g, ph, flag, f, sm, ec); break;
   }
 }
 

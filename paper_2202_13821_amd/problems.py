@@ -94,7 +94,7 @@ def project_separable(terms, shape, lo, hi, degree, widths=None):
 one = lambda x: np.ones_like(x)
 
 
-def tgv(shape, degree, gamma=1.4, mach=0.1):
+def tgv(shape, degree, gamma=1.4, mach=0.1, widths=None):
     p0 = 1.0 / (gamma * mach * mach)
     sin, cos = np.sin, np.cos
     c2 = lambda x: np.cos(2 * x)
@@ -111,7 +111,7 @@ def tgv(shape, degree, gamma=1.4, mach=0.1):
          (0.5, sq(sin), sq(cos), sq(cos)), (0.5, sq(cos), sq(sin), sq(cos))],
     ]
     lo, hi = (-math.pi,) * 3, (math.pi,) * 3
-    return project_separable(terms, shape, lo, hi, degree), lo, hi
+    return project_separable(terms, shape, lo, hi, degree, widths), lo, hi
 
 
 def advection(shape, degree, gamma=1.4, widths=None):

@@ -6,8 +6,10 @@ python -m paper_2202_13821_amd.profiling traffic <fetch counter_collection.csv> 
 python -m paper_2202_13821_amd.profiling counters <out.md> "<command prefix>" <counter_collection.csv>...
 
 `counters` summarises SQ/GRBM counter passes per kernel: VALU instructions
-per wavefront, VALU issue utilisation (VALU instructions x 4 cycles over
-4 SIMDs x 256 CUs x the kernel's GRBM_GUI_ACTIVE cycles / 8 XCDs), resident
+per wavefront, SIMD cycles per VALU instruction (4 SIMDs x 256 CUs x the
+kernel's GRBM_GUI_ACTIVE cycles / 8 XCDs, over the VALU instructions of all
+wavefronts; about 2.6 is the issue rate of FP32 instructions with VGPR
+operands on gfx950, 4 that of instructions reading an SGPR), resident
 wavefronts per SIMD, and the fraction of wave time spent waiting.
 
 `traffic` reads FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of every kernel,
@@ -128,7 +130,7 @@ def counters(out_md, command, *csvs):
                 float(_col(r, "Counter_Value", "Counter-Value")))
     avg = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in vals.items()}
     lines = ["# rocprofv3 counters per kernel", "", f"Command (one run per counter set): `{command}`", "",
-             "| kernel | VALU instr / wave | VALU issue util. | waves / SIMD | wait fraction | FP32 flop / wave | FP64 flop / wave |",
+             "| kernel | VALU instr / wave | SIMD cycles / VALU instr | waves / SIMD | wait fraction | FP32 flop / wave | FP64 flop / wave |",
              "|---|---|---|---|---|---|---|"]
     for k in sorted(avg):
         d = avg[k]
@@ -137,12 +139,12 @@ def counters(out_md, command, *csvs):
         w = d["SQ_WAVES"]
         cyc = d.get("GRBM_GUI_ACTIVE", 0.0) / 8.0  # summed over the 8 XCDs
         valu = d.get("SQ_INSTS_VALU", 0.0)
-        util = valu * 4.0 / (4 * 256 * cyc) if cyc else float("nan")
+        cpi = 4 * 256 * cyc / valu if cyc and valu else float("nan")
         occ = 4.0 * d["SQ_WAVE_CYCLES"] / cyc / 1024.0 if cyc and "SQ_WAVE_CYCLES" in d else float("nan")
         wait = d["SQ_WAIT_ANY"] / d["SQ_WAVE_CYCLES"] if "SQ_WAIT_ANY" in d else float("nan")
         f32 = 64 * d.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0) / w
         f64 = 64 * d.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) / w
-        lines.append(f"| `{k}` | {valu / w:.0f} | {util:.2f} | {occ:.2f} | {wait:.2f} | {f32:.3g} | {f64:.3g} |")
+        lines.append(f"| `{k}` | {valu / w:.0f} | {cpi:.2f} | {occ:.2f} | {wait:.2f} | {f32:.3g} | {f64:.3g} |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -9,6 +9,7 @@
 //   vop2_mul : v_mul_f32_e32 (x *= z)
 //   vop3_nfma: v_fma_f32 with a negated operand, all operands in VGPRs (x -= y * z)
 //   sgpr_fmac: v_fmac_f32_e32 with one scalar operand (x += y * a)
+//   lit_fmaak: v_fmaak_f32, a literal constant operand (x = x * y + K)
 //   fp64_fma : v_fma_f64
 // Build: python -m paper_2202_13821_amd.csrc.peakprobe (or hipcc as below);
 // run the binary on the GPU; it prints one line per form and grid size.
@@ -41,6 +42,8 @@ __global__ __launch_bounds__(256) void chains(T* out, int iters, T a, T b) {
         x[c] = __builtin_fmaf(-y[c], z, x[c]);  // VOP3 (negation modifier), all VGPRs
       else if constexpr (MODE == 4)
         x[c] = __builtin_fmaf(y[c], a, x[c]);  // v_fmac_f32 with one scalar operand
+      else if constexpr (MODE == 5)
+        x[c] = __builtin_fmaf(x[c], y[c], T(1.2345678));  // v_fmaak_f32: literal addend
       else
         x[c] = x[c] * z;
     }
@@ -84,6 +87,7 @@ int main() {
     rc |= run<float, 2>("vop2_mul", b, 10000, 1.0);
     rc |= run<float, 3>("vop3_nfma", b, 10000, 2.0);
     rc |= run<float, 4>("sgpr_fmac", b, 10000, 2.0);
+    rc |= run<float, 5>("lit_fmaak", b, 10000, 2.0);
     rc |= run<double, 0>("fp64_fma", b, 5000, 2.0);
   }
   return rc;

@@ -703,21 +703,50 @@ DGK_HD void face_finish_vjp(const Phys& ph, const FaceAcc<T>& acc, const T Fb[5]
   const double tau = ph.mu * ip0, xh = ph.half_dt_over_mu * p0;
   double al[6], be[6];
   time_coefficients(tau, xh, ph.dt, ph.inv_dt, al, be, ExpTabHolder<>::t.c);
-  const T* mm[6] = {m1, m2, m3, acc.m4, acc.m5, acc.m6};
-  double alb[6], beb[6];
+  // Reverse of the combination as face_finish computes it, in T with the FP64
+  // coefficients rounded once:
+  //   Ft = b0 d14 + b1 d25 + b2 m3 + b5 m6,
+  //   F  = m4 + a0 d14 + a1 d25 - tau m5 + a2 m3 + a5 m6,  d14 = m1 - m4, d25 = m2 - m5.
+  // With alpha_3 = 1 - alpha_0, alpha_4 = -tau - alpha_1, beta_3 = -beta_0,
+  // beta_4 = -beta_1, the cotangents of the independent coefficients are the
+  // dot products with d14, d25, m3, m6, and -tau m5 adds -Fb.m5 to that of tau.
+  T d14[5], d25[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    d14[k] = m1[k] - acc.m4[k];
+    d25[k] = m2[k] - acc.m5[k];
+  }
+  T fa0 = T(0), fa1 = T(0), fa2 = T(0), fa5 = T(0), fm5 = T(0);
+  T fb0 = T(0), fb1 = T(0), fb2 = T(0), fb5 = T(0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    if constexpr (NEED_F) {
+      fa0 += Fb[k] * d14[k];
+      fa1 += Fb[k] * d25[k];
+      fa2 += Fb[k] * m3[k];
+      fa5 += Fb[k] * acc.m6[k];
+      fm5 += Fb[k] * acc.m5[k];
+    }
+    fb0 += Ftb[k] * d14[k];
+    fb1 += Ftb[k] * d25[k];
+    fb2 += Ftb[k] * m3[k];
+    fb5 += Ftb[k] * acc.m6[k];
+  }
+  const double alb[6] = {double(fa0), double(fa1), double(fa2), 0.0, 0.0, double(fa5)};
+  const double beb[6] = {double(fb0), double(fb1), double(fb2), 0.0, 0.0, double(fb5)};
+  const T a0 = T(al[0]), a1 = T(al[1]), a2 = T(al[2]), a5 = T(al[5]), tT = T(tau);
+  const T b0 = T(be[0]), b1 = T(be[1]), b2 = T(be[2]), b5 = T(be[5]);
   T mb[6][5];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    double sa = 0.0, sbv = 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double f = NEED_F ? double(Fb[k]) : 0.0;
-      sa += f * double(mm[j][k]);
-      sbv += double(Ftb[k]) * double(mm[j][k]);
-      mb[j][k] = T(be[j] * double(Ftb[k]) + al[j] * f);
-    }
-    alb[j] = sa;
-    beb[j] = sbv;
+  for (int k = 0; k < 5; ++k) {
+    const T f = NEED_F ? Fb[k] : T(0);
+    const T d14b = a0 * f + b0 * Ftb[k], d25b = a1 * f + b1 * Ftb[k];
+    mb[0][k] = d14b;
+    mb[1][k] = d25b;
+    mb[2][k] = a2 * f + b2 * Ftb[k];
+    mb[3][k] = f - d14b;
+    mb[4][k] = -d25b - tT * f;
+    mb[5][k] = a5 * f + b5 * Ftb[k];
   }
   Prim<T> sb = prim_zero<T>();
   Grad<T> gb = grad_zero<T>();
@@ -726,7 +755,7 @@ DGK_HD void face_finish_vjp(const Phys& ph, const FaceAcc<T>& acc, const T Fb[5]
     gb.dT[0] -= T(ph.inv_pr_m1 * ph.mu * ph.cp * double(Fb[4]));
     mub -= ph.inv_pr_m1 * ph.cp * double(g.dT[0]) * double(Fb[4]);
   }
-  double taub = 0.0, xb = 0.0;
+  double taub = -double(fm5), xb = 0.0;
   time_coefficients_bwd(tau, xh, ph.dt, ph.inv_dt, alb, beb, taub, xb);
   double p0b = xb * ph.half_dt_over_mu - taub * ph.mu * ip0 * ip0;
   mub += taub * ip0;

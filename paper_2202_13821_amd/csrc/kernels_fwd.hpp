@@ -195,6 +195,14 @@ DGK_D float to_vgpr(float x) {
   return r;
 }
 DGK_D double to_vgpr(double x) { return x; }
+// The same, never merged with another copy of the same value (so that a copy
+// is made where it is used instead of being kept alive in between).
+DGK_D float to_vgpr_here(float x) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+DGK_D double to_vgpr_here(double x) { return x; }
 
 // Lanes per face block: 256, or 128 where the LDS columns of 256 lanes would
 // exceed the 160 KB of a CU (FP64 at P3).

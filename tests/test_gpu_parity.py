@@ -133,6 +133,24 @@ def test_residual_fp32_bulk(shape, k, nq, problem, mu, pr):
     assert eL <= tol and eLt <= 10 * tol
 
 
+@pytest.mark.parametrize("shape,k,nq,precision,tol", [((64, 3, 5), 2, 3, "fp64", 1e-11), ((128, 2, 3), 1, 2, "fp64", 1e-11),
+                                                     ((64, 3, 5), 2, 3, "fp32_bulk", 1e-4), ((64, 2, 6), 3, 3, "fp64", 1e-11)])
+def test_residual_whole_tile_rows(shape, k, nq, precision, tol):
+    """Rows of whole 64-cell tiles (every wavefront one aligned x segment),
+    with a ragged z extent."""
+    say("residual whole tile rows", shape, k, nq, precision)
+    rng = np.random.default_rng(310 + k)
+    q = IN.random_field(rng, shape, P.nmodes(k), amp=0.03)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.3, 0.7)
+    s, c = pair(shape, k, lo, hi, nq=nq, mu=0.01, pr=0.72, precision=precision)
+    L, Lt = s.residual(to_dev(q), 3e-3)
+    Lo, Lto = O.residual(c, q, 3e-3)
+    eL, eLt = rel_l2_groups(to_np(L), Lo), rel_l2_groups(to_np(Lt), Lto)
+    say("  rel L2 of L, Lt:", eL, eLt)
+    assert eL <= tol and eLt <= 10 * tol
+    s.check()
+
+
 # ---------------------------------------------------------------------------
 # full steps
 # ---------------------------------------------------------------------------
@@ -165,6 +183,20 @@ def test_step_tgv_8(precision, tol):
     assert e <= tol
     # the change over the steps is matched too (not only the large background)
     assert ed <= (1e-9 if precision == "fp64" else 5e-2)
+
+
+def test_step_whole_tile_rows_fp64():
+    say("whole tile rows steps")
+    rng = np.random.default_rng(410)
+    shape = (64, 2, 7)
+    q0 = IN.random_field(rng, shape, 10, amp=0.03)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 0.8, 0.6)
+    s, c = pair(shape, 2, lo, hi, mu=0.005, pr=0.72)
+    q = to_dev(q0)
+    s.step(q, 2e-3, 2)
+    qo = O.step(c, q0, 2e-3, 2)
+    assert rel_l2(to_np(q) - q0, qo - q0) <= 1e-9
+    assert rel_l2(to_np(q), qo) <= 1e-10
 
 
 def test_step_random_ragged_fp64():

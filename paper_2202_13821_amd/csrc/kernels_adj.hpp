@@ -184,26 +184,18 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
   double mb = 0.0;
 #pragma unroll 1
   for (int qf = 0; qf < NQ2; ++qf) {
-    // this side's trace (local frame); the basis values as VGPR copies (an
-    // FP32 FMA reading an SGPR issues at half the rate)
+    // this side's trace (local frame)
     T qs[5], dqs[3][5];
-    T bv[NT], bd1[NT], bd2[NT];
-    static_for<NT>([&](auto tc) {
-      constexpr int t = decltype(tc)::value;
-      bv[t] = to_vgpr_here(TB::t.val[qf][t]);
-      bd1[t] = (tmd.e[t][0] > 0) ? to_vgpr_here(TB::t.d1[qf][t]) : T(0);
-      bd2[t] = (tmd.e[t][1] > 0) ? to_vgpr_here(TB::t.d2[qf][t]) : T(0);
-    });
 #pragma unroll
     for (int vl = 0; vl < 5; ++vl) {
       T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0);
       static_for<NT>([&](auto tc) {
         constexpr int t = decltype(tc)::value;
         const T c = ct[vmap[vl]][t];
-        v0 += c * bv[t];
-        if constexpr (tmd.e[t][0] > 0) v1 += c * bd1[t];
-        if constexpr (tmd.e[t][1] > 0) v2 += c * bd2[t];
-        if constexpr (t < NT1) vn += cn[vmap[vl]][t] * bv[t];
+        v0 += c * TB::t.val[qf][t];
+        if constexpr (tmd.e[t][0] > 0) v1 += c * TB::t.d1[qf][t];
+        if constexpr (tmd.e[t][1] > 0) v2 += c * TB::t.d2[qf][t];
+        if constexpr (t < NT1) vn += cn[vmap[vl]][t] * TB::t.val[qf][t];
       });
       qs[vl] = v0;
       dqs[0][vl] = vn * sn;
@@ -222,14 +214,11 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
     pair_sum(&acc.m6[0], 5);
     // Fbar_b at this point = sum_m phi_m(qf) Phibar[m], local frame
     T Fb[5], Ftb[5];
-    T pv[NT];
-#pragma unroll
-    for (int m = 0; m < NT; ++m) pv[m] = to_vgpr_here(FT::t.phi[m][qf]);
 #pragma unroll
     for (int vl = 0; vl < 5; ++vl) {
       T sp = T(0);
 #pragma unroll
-      for (int m = 0; m < NT; ++m) sp += pv[m] * ph_[vmap[vl]][m];
+      for (int m = 0; m < NT; ++m) sp += FT::t.phi[m][qf] * ph_[vmap[vl]][m];
       if constexpr (NEED_F) {
         const T other = pair_swap(sp);
         Fb[vl] = side ? other : sp;
@@ -249,23 +238,17 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
 #pragma unroll
     for (int i = 0; i < 3; ++i) zero5(dqb[i]);
     face_side_vjp(ph, qs, dqs, accb, qb, dqb, sg);
-    // transposed trace evaluation (fresh VGPR copies of the basis values)
-    static_for<NT>([&](auto tc) {
-      constexpr int t = decltype(tc)::value;
-      bv[t] = to_vgpr_here(TB::t.val[qf][t]);
-      bd1[t] = (tmd.e[t][0] > 0) ? to_vgpr_here(TB::t.d1[qf][t]) : T(0);
-      bd2[t] = (tmd.e[t][1] > 0) ? to_vgpr_here(TB::t.d2[qf][t]) : T(0);
-    });
+    // transposed trace evaluation
 #pragma unroll
     for (int vl = 0; vl < 5; ++vl) {
       const T bn = dqb[0][vl] * sn, b1 = dqb[1][vl] * s1, b2 = dqb[2][vl] * s2;
       static_for<NT>([&](auto tc) {
         constexpr int t = decltype(tc)::value;
-        T a = qb[vl] * bv[t];
-        if constexpr (tmd.e[t][0] > 0) a += b1 * bd1[t];
-        if constexpr (tmd.e[t][1] > 0) a += b2 * bd2[t];
+        T a = qb[vl] * TB::t.val[qf][t];
+        if constexpr (tmd.e[t][0] > 0) a += b1 * TB::t.d1[qf][t];
+        if constexpr (tmd.e[t][1] > 0) a += b2 * TB::t.d2[qf][t];
         ctb[vmap[vl]][t] += a;
-        if constexpr (t < NT1) cnb[vmap[vl]][t] += bn * bv[t];
+        if constexpr (t < NT1) cnb[vmap[vl]][t] += bn * TB::t.val[qf][t];
       });
     }
   }

@@ -185,25 +185,6 @@ struct FaceLds {
   T st[4][NTH];  // 2 / width along the normal (lower, upper cell) and the two tangents
 };
 
-// A wavefront-uniform FP32 value moved to a VGPR: on gfx950 an FP32 VALU
-// instruction that reads an SGPR issues at the 4-cycle rate, one whose
-// operands are all VGPRs at about 2.6 cycles, so a basis value that feeds ten
-// FMAs is copied once.  FP64 values are returned unchanged.
-DGK_D float to_vgpr(float x) {
-  float r;
-  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-  return r;
-}
-DGK_D double to_vgpr(double x) { return x; }
-// The same, never merged with another copy of the same value (so that a copy
-// is made where it is used instead of being kept alive in between).
-DGK_D float to_vgpr_here(float x) {
-  float r;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-  return r;
-}
-DGK_D double to_vgpr_here(double x) { return x; }
-
 // Lanes per face block: 256, or 128 where the LDS columns of 256 lanes would
 // exceed the 160 KB of a CU (FP64 at P3).
 template <class T, int K>
@@ -304,14 +285,6 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
     __asm__ __volatile__("" ::: "memory");
     FaceAcc<T> fa;
     face_acc_zero(fa);
-    // this point's tangential basis values and derivatives
-    T bv[NT], b1[NT], b2[NT];
-    static_for<NT>([&](auto tc) {
-      constexpr int t = decltype(tc)::value;
-      bv[t] = to_vgpr(TB::t.val[qf][t]);
-      b1[t] = (tmd.e[t][0] > 0) ? to_vgpr(TB::t.d1[qf][t]) : T(0);
-      b2[t] = (tmd.e[t][1] > 0) ? to_vgpr(TB::t.d2[qf][t]) : T(0);
-    });
     static_for<2>([&](auto sc) {
       constexpr int side = decltype(sc)::value;
       // trace of this side at the point: Q and its derivatives along (n, t1, t2)
@@ -328,16 +301,16 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
             c = ct0[vmap[vl]][t];
           else
             c = sm.x[vmap[vl] * NT + t][tid];
-          v0 += c * bv[t];
-          if constexpr (tmd.e[t][0] > 0) v1 += c * b1[t];
-          if constexpr (tmd.e[t][1] > 0) v2 += c * b2[t];
+          v0 += c * TB::t.val[qf][t];
+          if constexpr (tmd.e[t][0] > 0) v1 += c * TB::t.d1[qf][t];
+          if constexpr (tmd.e[t][1] > 0) v2 += c * TB::t.d2[qf][t];
           if constexpr (t < NT1) {
             T cnv;
             if constexpr (side == 0)
               cnv = cn0[vmap[vl]][t];
             else
               cnv = sm.c1[5 * NT + vmap[vl] * NT1 + t][tid];
-            vn += cnv * bv[t];
+            vn += cnv * TB::t.val[qf][t];
           }
         });
         qs[vl] = v0;
@@ -358,7 +331,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
     // record component order: (F|Ft, global variable, tangential mode)
     static_for<NT>([&](auto mc) {
       constexpr int m = decltype(mc)::value;
-      const T p = to_vgpr(FT::t.phi[m][qf]);
+      const T p = FT::t.phi[m][qf];
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
         if constexpr (NEED_F) sm.x[vmap[vl] * NT + m][tid] += p * F[vl];

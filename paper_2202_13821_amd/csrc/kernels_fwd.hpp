@@ -164,12 +164,14 @@ DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
 // --------------------------------------------------------------------------
 // Face kernel.  One lane per face: the face between cell f (lower side) and
 // its upper neighbour along D, 64 faces (one tile of lower cells) per
-// wavefront.  The lane keeps the coefficients of both cells in registers and
-// visits the face points in a loop that is uniform across the wavefront
-// (trace basis and projection weights by scalar loads); per point the traces
-// of both sides, the gas-kinetic face flux, and its projection on the
-// tangential modes accumulated in registers.  Each record component is then
-// stored as one row of the tile.
+// wavefront.  The lane reduces the coefficients of both cells to their
+// face-restricted coefficients (registers for the lower cell, its own LDS
+// column for the upper one) and visits the face points in a loop that is
+// uniform across the wavefront (trace basis and projection weights by scalar
+// loads); per point the traces of both sides, the gas-kinetic face flux, and
+// its projection on the tangential modes (the Ft part in registers, the F
+// part in the LDS column).  Each record component is then stored as one row
+// of the tile.
 // --------------------------------------------------------------------------
 // LDS of one face block (each lane uses only its own column, so no barrier
 // is needed): the upper cell's face-restricted coefficients, and in stage 1

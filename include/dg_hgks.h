@@ -6,7 +6,8 @@
  * implementation", arXiv 2202.13821.
  *
  * Problem (Section 3): on a periodic Cartesian box [lo, hi]^3 split into
- * nx*ny*nz equal cells, the conservative variables Q = (rho, rho U, rho V,
+ * nx*ny*nz cells (equal, or a separable non-uniform mesh given by per-axis
+ * cell widths, as in the mapped meshes of Section 5.1), the conservative variables Q = (rho, rho U, rho V,
  * rho W, rho E) are expanded per cell in the P_k Legendre basis (Eq.
  * (expansion)); the ODE system dQ/dt = M^{-1} R(Q) = L(Q) of Eqs. (DG2) and
  * (operator) is integrated with Eq. (two-stage).  Face fluxes follow Eq.
@@ -22,7 +23,9 @@
  * modes ordered by total degree s = 0..k, then nx from s down to 0, then ny
  * from s - nx down to 0 (P1: 000 100 010 001; P2 adds 200 110 101 020 011 002).
  * Mode 0 is the cell average.  Cell (i, j, k) covers
- * [lo + i dx, lo + (i+1) dx] x ... with dx = (hi - lo) / n per axis.
+ * [lo + i dx, lo + (i+1) dx] x ... with dx = (hi - lo) / n per axis, or on a
+ * non-uniform mesh [lo + w_0 + ... + w_{i-1}, ... + w_i] x ... with the
+ * widths w of dg_hgks_params.cell_widths.
  *
  * Ownership: the caller owns every device buffer (coefficients, checkpoints,
  * adjoint seeds and outputs, workspace); the library never allocates or frees

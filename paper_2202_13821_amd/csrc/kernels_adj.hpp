@@ -93,13 +93,29 @@ DGK_D long long frec_index(int d, int side, long long face, int vm, int nvm, lon
 // Lanes per adjoint face block: 128 faces x 2 sides.
 constexpr int kAdjFaceThreads = 256;
 
+// FP64 up to P2: the lane's face-restricted coefficients and record cotangent
+// live in its LDS column (read where used) instead of registers.  The FP64
+// kernel runs one wavefront per SIMD either way; the 150 VGPRs this frees cut
+// its spills to scratch.  FP32 keeps them in registers (its working set fits).
+template <class T, int K>
+struct AdjFaceLds {
+  static constexpr bool use = sizeof(T) == 8 && K <= 2;
+  static constexpr int NT = ntan(K), NT1 = ntan(K - 1);
+  T ct[5 * NT][kAdjFaceThreads];
+  T cn[5 * NT1][kAdjFaceThreads];
+  T ph[5 * NT][kAdjFaceThreads];
+};
+struct NoAdjFaceLds {};
+template <class T, int K>
+using AdjFaceSmem = std::conditional_t<AdjFaceLds<T, K>::use, AdjFaceLds<T, K>, NoAdjFaceLds>;
+
 // --------------------------------------------------------------------------
 // Adjoint face kernel.  Lane 2j + s of a block handles side s of face
 // f0 + j (s = 0: the lower cell, half space u > 0; s = 1: the upper cell).
 // --------------------------------------------------------------------------
 template <class T, int K, int NQ, int STAGE, int D>
 DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double* __restrict__ frec, const Geo& g,
-                         const Phys& ph, long long f, int side, double& mub) {
+                         const Phys& ph, long long f, int side, double& mub, AdjFaceSmem<T, K>& sm) {
   constexpr int NM = nmodes(K), NT = ntan(K), NT1 = ntan(K - 1), NQ2 = NQ * NQ;
   constexpr bool NEED_F = (STAGE == 1);
   constexpr int NF = NEED_F ? 2 : 1;
@@ -168,6 +184,31 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
       }
     }
 
+  // the coefficients and record cotangent as used in the point loop
+  constexpr bool LDS = AdjFaceLds<T, K>::use;
+  const int tid = threadIdx.x;
+  if constexpr (LDS) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        sm.ct[v * NT + t][tid] = ct[v][t];
+        sm.ph[v * NT + t][tid] = ph_[v][t];
+      }
+#pragma unroll
+      for (int t = 0; t < NT1; ++t) sm.cn[v * NT1 + t][tid] = cn[v][t];
+    }
+  }
+  auto CT = [&](int v, int t) -> T {
+    if constexpr (LDS) return sm.ct[v * NT + t][tid]; else return ct[v][t];
+  };
+  auto CN = [&](int v, int t) -> T {
+    if constexpr (LDS) return sm.cn[v * NT1 + t][tid]; else return cn[v][t];
+  };
+  auto PH = [&](int v, int m) -> T {
+    if constexpr (LDS) return sm.ph[v * NT + m][tid]; else return ph_[v][m];
+  };
+
   // cotangents of ct, cn
   T ctb[5][NT], cnb[5][NT1];
 #pragma unroll
@@ -184,6 +225,8 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
   double mb = 0.0;
 #pragma unroll 1
   for (int qf = 0; qf < NQ2; ++qf) {
+    // keeps the LDS columns in LDS: no load moves across this point
+    __asm__ __volatile__("" ::: "memory");
     // this side's trace (local frame)
     T qs[5], dqs[3][5];
 #pragma unroll
@@ -191,11 +234,11 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
       T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0);
       static_for<NT>([&](auto tc) {
         constexpr int t = decltype(tc)::value;
-        const T c = ct[vmap[vl]][t];
+        const T c = CT(vmap[vl], t);
         v0 += c * TB::t.val[qf][t];
         if constexpr (tmd.e[t][0] > 0) v1 += c * TB::t.d1[qf][t];
         if constexpr (tmd.e[t][1] > 0) v2 += c * TB::t.d2[qf][t];
-        if constexpr (t < NT1) vn += cn[vmap[vl]][t] * TB::t.val[qf][t];
+        if constexpr (t < NT1) vn += CN(vmap[vl], t) * TB::t.val[qf][t];
       });
       qs[vl] = v0;
       dqs[0][vl] = vn * sn;
@@ -218,7 +261,7 @@ DGK_D void adj_face_lane(const T* __restrict__ q, const AdjIn<STAGE>& in, double
     for (int vl = 0; vl < 5; ++vl) {
       T sp = T(0);
 #pragma unroll
-      for (int m = 0; m < NT; ++m) sp += FT::t.phi[m][qf] * ph_[vmap[vl]][m];
+      for (int m = 0; m < NT; ++m) sp += FT::t.phi[m][qf] * PH(vmap[vl], m);
       if constexpr (NEED_F) {
         const T other = pair_swap(sp);
         Fb[vl] = side ? other : sp;
@@ -284,10 +327,11 @@ __global__ __launch_bounds__(kAdjFaceThreads) void adj_face_kernel(const T* __re
   const long long f = (long long)(lb - d * nb) * FPB + (threadIdx.x >> 1);
   const int side = threadIdx.x & 1;
   double mub = 0.0;
+  __shared__ AdjFaceSmem<T, K> sm;
   switch (d) {
-    case 0: adj_face_lane<T, K, NQ, STAGE, 0>(q, in, frec, g, ph, f, side, mub); break;
-    case 1: adj_face_lane<T, K, NQ, STAGE, 1>(q, in, frec, g, ph, f, side, mub); break;
-    default: adj_face_lane<T, K, NQ, STAGE, 2>(q, in, frec, g, ph, f, side, mub); break;
+    case 0: adj_face_lane<T, K, NQ, STAGE, 0>(q, in, frec, g, ph, f, side, mub, sm); break;
+    case 1: adj_face_lane<T, K, NQ, STAGE, 1>(q, in, frec, g, ph, f, side, mub, sm); break;
+    default: adj_face_lane<T, K, NQ, STAGE, 2>(q, in, frec, g, ph, f, side, mub, sm); break;
   }
   block_add_mu<kAdjFaceThreads>(mub, mu_part, lb, red);
 }

@@ -89,17 +89,17 @@ def time_path(precision, n, steps, warmup, timing=True, k=2, nq=0, mapped=False)
     return (t1 - t0) / steps, kern, q, s
 
 
-def adjoint_ratio(precision, n=32, nsteps=200, stride=15):
-    """adj/fwd on a P2 Taylor-Green run (default: the 32^3, 200-step adjoint
+def adjoint_ratio(precision, n=32, nsteps=200, stride=15, k=2, nq=0):
+    """adj/fwd on a Taylor-Green run (default: the P2 32^3, 200-step adjoint
     configuration): wall time of the gradient call (segment recomputation +
     reverse sweep) over that of the checkpointing forward call."""
     import torch
 
     from paper_2202_13821_amd import Solver, kinetic_energy, problems
 
-    q0, lo, hi = problems.tgv((n, n, n), 2)
-    dt = problems.tgv_dt(n)
-    s = Solver((n, n, n), lo, hi, 2, mu=1.0 / 1600.0, prandtl=0.72, precision=precision, device="cuda:0",
+    q0, lo, hi = problems.tgv((n, n, n), k)
+    dt = problems.tgv_dt(n, cfl=0.15 if k < 3 else 0.08)
+    s = Solver((n, n, n), lo, hi, k, nq=nq, mu=1.0 / 1600.0, prandtl=0.72, precision=precision, device="cuda:0",
                max_stride=stride)
     ck = s.new_checkpoints(nsteps, stride)
     q = torch.as_tensor(q0, device="cuda:0")
@@ -123,7 +123,8 @@ def adjoint_ratio(precision, n=32, nsteps=200, stride=15):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     return {"fwd_s": t1 - t0, "adj_s": t3 - t2, "adj_over_fwd": (t3 - t2) / (t1 - t0),
-            "workload": f"P2 TGV {n}^3, {nsteps} steps, checkpoint stride {stride}"}
+            "workload": f"P{k} TGV {n}^3{'' if not nq else f', {nq} Gauss points'}, {nsteps} steps, "
+                        f"checkpoint stride {stride}"}
 
 
 def kernel_source_hash():
@@ -187,7 +188,9 @@ def main():
 
     if a.adjoint_only:
         print(json.dumps({"adjoint": {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64"),
-                                      "fp32_bulk_128": adjoint_ratio("fp32_bulk", n=a.n, nsteps=6, stride=3)}}),
+                                      "fp32_bulk_128": adjoint_ratio("fp32_bulk", n=a.n, nsteps=6, stride=3),
+                                      "p3_fp32_bulk": adjoint_ratio("fp32_bulk", nsteps=50, stride=7, k=3),
+                                      "p3_fp64": adjoint_ratio("fp64", nsteps=50, stride=7, k=3)}}),
               flush=True)
         return
     n = a.n
@@ -291,6 +294,10 @@ def main():
     if not a.no_adjoint:
         out["adjoint"] = {"fp32_bulk": adjoint_ratio("fp32_bulk"), "fp64": adjoint_ratio("fp64"),
                           "fp32_bulk_128": adjoint_ratio("fp32_bulk", n=n, nsteps=6, stride=3)}
+        if not a.no_rules:
+            # P3 (4 Gauss points), 32^3, 50 steps
+            out["adjoint"]["p3_fp32_bulk"] = adjoint_ratio("fp32_bulk", nsteps=50, stride=7, k=3)
+            out["adjoint"]["p3_fp64"] = adjoint_ratio("fp64", nsteps=50, stride=7, k=3)
         out["adj_over_fwd"] = out["adjoint"]["fp32_bulk"]["adj_over_fwd"]
     if a.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)

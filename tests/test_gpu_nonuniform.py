@@ -89,7 +89,7 @@ def test_nonuniform_free_stream_and_conservation():
     assert np.abs(to_np(q) - qu).max() <= 1e-12
 
 
-@pytest.mark.parametrize("k,nq", [(2, 3), (3, 3)])
+@pytest.mark.parametrize("k,nq", [(2, 3), (3, 3), (2, 2)])
 def test_nonuniform_adjoint_vs_oracle_dual_fp64(k, nq):
     say("nonuniform adjoint", k, nq)
     rng = np.random.default_rng(940 + k)
@@ -183,3 +183,27 @@ def test_mapped_mesh_error_ratio_matches_paper(k, paper_ratio):
         ratios.append(em / eu)
     say("  ratios (8^3, 16^3)", ratios, "paper 8^3", paper_ratio)
     assert abs(ratios[0] / paper_ratio - 1.0) < 0.03
+
+
+def test_nonuniform_adjoint_fp32_bulk_vs_fp64():
+    """FP32-bulk adjoint on a random non-uniform mesh against the FP64 adjoint
+    (the bar of the uniform-mesh FP32-bulk adjoint)."""
+    rng = np.random.default_rng(960)
+    shape, n, stride = (6, 5, 4), 4, 2
+    w = IN.random_widths(rng, shape, LO, HI)
+    q0 = IN.random_field(rng, shape, 10, amp=0.04)
+    out = {}
+    for prec in ("fp64", "fp32_bulk"):
+        s, _ = pair(shape, 2, LO, HI, mu=0.01, pr=0.72, precision=prec, max_stride=stride, widths=w)
+        ck = s.new_checkpoints(n, stride)
+        q = to_dev(q0)
+        s.step(q, 1e-3, n, ck, stride)
+        qN = q.detach().clone().requires_grad_(True)
+        (g,) = torch.autograd.grad(kinetic_energy(qN, s), qN)
+        q0b, mub = s.adjoint(ck, stride, 1e-3, n, g.contiguous())
+        out[prec] = (to_np(q0b), mub)
+    g32, g64 = out["fp32_bulk"][0], out["fp64"][0]
+    e = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    emu = abs(out["fp32_bulk"][1] - out["fp64"][1]) / abs(out["fp64"][1])
+    say("  full-gradient rel L2, rel dJ/dmu:", e, emu)
+    assert e <= 1e-3 and emu <= 1e-3

@@ -165,25 +165,24 @@ DGK_D unsigned xcd_block(unsigned b, unsigned nb) {
 // Face kernel.  One lane per face: the face between cell f (lower side) and
 // its upper neighbour along D, 64 faces (one tile of lower cells) per
 // wavefront.  The lane reduces the coefficients of both cells to their
-// face-restricted coefficients (registers for the lower cell, its own LDS
-// column for the upper one) and visits the face points in a loop that is
-// uniform across the wavefront (trace basis and projection weights by scalar
-// loads); per point the traces of both sides, the gas-kinetic face flux, and
-// its projection on the tangential modes (the Ft part in registers, the F
-// part in the LDS column).  Each record component is then stored as one row
+// face-restricted coefficients (its own LDS column, except the lower cell's
+// normal-derivative coefficients, kept in registers) and visits the face
+// points in a loop that is uniform across the wavefront (trace basis and
+// projection weights by scalar loads); per point the traces of both sides,
+// the gas-kinetic face flux, and its projection on the tangential modes
+// accumulated in registers.  Each record component is then stored as one row
 // of the tile.
 // --------------------------------------------------------------------------
 // LDS of one face block (each lane uses only its own column, so no barrier
-// is needed): the upper cell's face-restricted coefficients, and in stage 1
-// the F part of the record accumulators, in stage 2 the lower cell's trace
-// coefficients; and the cell-width scales of the face.  At 2 x 256 lanes per
-// CU this is 79 floats per lane (of 80).
+// is needed): the upper cell's face-restricted coefficients, the lower cell's
+// trace coefficients, and the cell-width scales of the face.  At 2 x 256
+// lanes per CU this is 79 floats per lane (of 80).
 template <class T, int K, bool NEED_F, int NTH>
 struct FaceLds {
   static constexpr int NT = ntan(K), NT1 = ntan(K - 1);
   static constexpr int NC = 5 * (NT + NT1);
   T c1[NC][NTH];
-  T x[5 * NT][NTH];
+  T x[5 * NT][NTH];  // the lower cell's trace coefficients
   T st[4][NTH];  // 2 / width along the normal (lower, upper cell) and the two tangents
 };
 
@@ -229,9 +228,10 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
   // and of its normal derivative, cn[v][t] = sum_{e_D} c[v][n] P'_{e_D}(+-1)
   // (tangential degree <= K - 1), with P_e(+1) = 1, P_e(-1) = (-1)^e,
   // P'_e(+1) = e(e+1)/2, P'_e(-1) = (-1)^(e+1) e(e+1)/2.
-  // Side 1 (upper cell) goes to LDS; side 0 (lower cell) stays in registers,
-  // except its trace coefficients ct in stage 2.
-  T ct0[5][NT], cn0[5][NT1];
+  // Side 1 (upper cell) goes to LDS; side 0 (lower cell) keeps its normal-
+  // derivative coefficients cn in registers and its trace coefficients ct in
+  // LDS (read-only in the point loop).
+  T cn0[5][NT1];
   static_for<2>([&](auto sc) {
     constexpr int side = decltype(sc)::value;
     const long long cell = side ? fu : fl;
@@ -255,8 +255,6 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       for (int t = 0; t < NT; ++t) {
         if constexpr (side == 1)
           sm.c1[v * NT + t][tid] = ct[t];
-        else if constexpr (NEED_F)
-          ct0[v][t] = ct[t];
         else
           sm.x[v * NT + t][tid] = ct[t];
       }
@@ -269,14 +267,14 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       }
     }
   });
-  // record accumulators: Ft part in registers, F part (stage 1) in LDS
-  T acc[5][NT];
+  // record accumulators (registers): Ft, and F in stage 1
+  T acc[5][NT], accF[NEED_F ? 5 : 1][NT];
 #pragma unroll
   for (int r = 0; r < 5; ++r)
 #pragma unroll
     for (int m = 0; m < NT; ++m) {
       acc[r][m] = T(0);
-      if constexpr (NEED_F) sm.x[r * NT + m][tid] = T(0);
+      if constexpr (NEED_F) accF[r][m] = T(0);
     }
   using TB = TanBasisHolder<T, K, NQ>;
   constexpr TanModes<K> tmd{};
@@ -299,8 +297,6 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
           T c;
           if constexpr (side == 1)
             c = sm.c1[vmap[vl] * NT + t][tid];
-          else if constexpr (NEED_F)
-            c = ct0[vmap[vl]][t];
           else
             c = sm.x[vmap[vl] * NT + t][tid];
           v0 += c * TB::t.val[qf][t];
@@ -336,7 +332,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       const T p = FT::t.phi[m][qf];
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
-        if constexpr (NEED_F) sm.x[vmap[vl] * NT + m][tid] += p * F[vl];
+        if constexpr (NEED_F) accF[vmap[vl]][m] += p * F[vl];
         acc[vmap[vl]][m] += p * Ft[vl];
       }
     });
@@ -349,7 +345,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
   for (int r = 0; r < 5; ++r)
 #pragma unroll
     for (int m = 0; m < NT; ++m) {
-      if constexpr (NEED_F) out[(r * NT + m) * 64] = sm.x[r * NT + m][tid];
+      if constexpr (NEED_F) out[(r * NT + m) * 64] = accF[r][m];
       out[(((NF - 1) * 5 + r) * NT + m) * 64] = acc[r][m];
     }
 }

@@ -434,14 +434,14 @@ DGK_HD void mat_Gw(const T* M, const Transverse<T>& t, T G[15]) {
   G[14] = T(0.25) * (t.W * M[5] + T(2) * t.wr * M[3] + t.wr2 * M[1]);
 }
 
-// y += r * S x for a symmetric S stored as above
+// y += S x for a symmetric S stored as above
 template <class T>
-DGK_HD void sym_mv_acc(const T S[15], const T x[5], T r, T y[5]) {
-  y[0] += r * (S[0] * x[0] + S[1] * x[1] + S[2] * x[2] + S[3] * x[3] + S[4] * x[4]);
-  y[1] += r * (S[1] * x[0] + S[5] * x[1] + S[6] * x[2] + S[7] * x[3] + S[8] * x[4]);
-  y[2] += r * (S[2] * x[0] + S[6] * x[1] + S[9] * x[2] + S[10] * x[3] + S[11] * x[4]);
-  y[3] += r * (S[3] * x[0] + S[7] * x[1] + S[10] * x[2] + S[12] * x[3] + S[13] * x[4]);
-  y[4] += r * (S[4] * x[0] + S[8] * x[1] + S[11] * x[2] + S[13] * x[3] + S[14] * x[4]);
+DGK_HD void sym_mv_acc(const T S[15], const T x[5], T y[5]) {
+  y[0] += S[0] * x[0] + S[1] * x[1] + S[2] * x[2] + S[3] * x[3] + S[4] * x[4];
+  y[1] += S[1] * x[0] + S[5] * x[1] + S[6] * x[2] + S[7] * x[3] + S[8] * x[4];
+  y[2] += S[2] * x[0] + S[6] * x[1] + S[9] * x[2] + S[10] * x[3] + S[11] * x[4];
+  y[3] += S[3] * x[0] + S[7] * x[1] + S[10] * x[2] + S[12] * x[3] + S[13] * x[4];
+  y[4] += S[4] * x[0] + S[8] * x[1] + S[11] * x[2] + S[13] * x[3] + S[14] * x[4];
 }
 
 // sg = +1: lower cell (half space u > 0); sg = -1: upper cell (u < 0).
@@ -451,19 +451,14 @@ DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>
   const Prim<T> s = primitive(q, gm1);
   bad |= int(unphysical(s));
   const Solver5<T> S(s, K, T(ph.inv_k3));
-  const T ir = s.ir;
-  // slopes: <a_i psi> = dQ/dn_i / rho, time slope from the compatibility condition
-  T a[3][5], A[5], b[5];
+  // slopes times the density: <a_i psi> = dQ/dn_i / rho and the solve is
+  // linear, so ra_i = rho a_i solves <ra_i psi> = dQ/dn_i; likewise rA = rho A
+  // from the compatibility condition <rA psi> = -sum_e J_e dQ/dx_e
+  T ra[3][5], rA[5], b[5];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[k] = dq[i][k] * ir;
-    S(b, a[i]);
-  }
+  for (int i = 0; i < 3; ++i) S(dq[i], ra[i]);
   euler_dt(s, q, gm1, dq, b);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) b[k] *= ir;
-  S(b, A);
+  S(b, rA);
   // half-space moments of the normal velocity, transverse Gaussian moments
   T M[7];
   mom_half(s.U, s.th, sg, M);
@@ -477,20 +472,20 @@ DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>
   acc.Q0[3] += r * H[3];
   acc.Q0[4] += r * H[4];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) sym_mv_acc(H, a[i], r, acc.dQ0[i]);
+  for (int i = 0; i < 3; ++i) sym_mv_acc(H, ra[i], acc.dQ0[i]);
   mat_H<1>(M, tr, H);  // <u psi psi^T>
   acc.m4[0] += r * H[0];
   acc.m4[1] += r * H[1];
   acc.m4[2] += r * H[2];
   acc.m4[3] += r * H[3];
   acc.m4[4] += r * H[4];
-  sym_mv_acc(H, A, r, acc.m6);
+  sym_mv_acc(H, rA, acc.m6);
   mat_H<2>(M, tr, H);  // <u^2 psi psi^T>
-  sym_mv_acc(H, a[0], r, acc.m5);
+  sym_mv_acc(H, ra[0], acc.m5);
   mat_Gv(M, tr, H);  // <u v psi psi^T>
-  sym_mv_acc(H, a[1], r, acc.m5);
+  sym_mv_acc(H, ra[1], acc.m5);
   mat_Gw(M, tr, H);  // <u w psi psi^T>
-  sym_mv_acc(H, a[2], r, acc.m5);
+  sym_mv_acc(H, ra[2], acc.m5);
 }
 
 // ec: the constants of exp_neg_tab (LDS in the face kernel).

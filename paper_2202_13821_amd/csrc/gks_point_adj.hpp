@@ -547,54 +547,37 @@ DGK_HD void mat_Gw_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb
   tb.wr2 += q * M[1] * Gb[14];
 }
 
-// Reverse of y += r S x (S symmetric, upper triangle in row order): adds the
-// cotangents of S, x and r.  With z = S ybar: xbar += r z, rbar += x.z,
-// Sbar_kj += r (ybar_k x_j + ybar_j x_k) (k < j), Sbar_kk += r ybar_k x_k.
+// Reverse of y += S x (S symmetric, upper triangle in row order): adds the
+// cotangents of S and x.  xbar += S ybar, Sbar_kj += ybar_k x_j + ybar_j x_k
+// (k < j), Sbar_kk += ybar_k x_k.
 template <class T>
-DGK_HD void sym_mv_bwd(const T S[15], const T x[5], T r, const T yb[5], T Sb[15], T xb[5], T& rb) {
-  T z[5];
-  z[0] = S[0] * yb[0] + S[1] * yb[1] + S[2] * yb[2] + S[3] * yb[3] + S[4] * yb[4];
-  z[1] = S[1] * yb[0] + S[5] * yb[1] + S[6] * yb[2] + S[7] * yb[3] + S[8] * yb[4];
-  z[2] = S[2] * yb[0] + S[6] * yb[1] + S[9] * yb[2] + S[10] * yb[3] + S[11] * yb[4];
-  z[3] = S[3] * yb[0] + S[7] * yb[1] + S[10] * yb[2] + S[12] * yb[3] + S[13] * yb[4];
-  z[4] = S[4] * yb[0] + S[8] * yb[1] + S[11] * yb[2] + S[13] * yb[3] + S[14] * yb[4];
-  T d = T(0);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    xb[k] += r * z[k];
-    d += x[k] * z[k];
-  }
-  rb += d;
-  T u[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) u[k] = r * yb[k];
+DGK_HD void sym_mv_bwd(const T S[15], const T x[5], const T yb[5], T Sb[15], T xb[5]) {
+  xb[0] += S[0] * yb[0] + S[1] * yb[1] + S[2] * yb[2] + S[3] * yb[3] + S[4] * yb[4];
+  xb[1] += S[1] * yb[0] + S[5] * yb[1] + S[6] * yb[2] + S[7] * yb[3] + S[8] * yb[4];
+  xb[2] += S[2] * yb[0] + S[6] * yb[1] + S[9] * yb[2] + S[10] * yb[3] + S[11] * yb[4];
+  xb[3] += S[3] * yb[0] + S[7] * yb[1] + S[10] * yb[2] + S[12] * yb[3] + S[13] * yb[4];
+  xb[4] += S[4] * yb[0] + S[8] * yb[1] + S[11] * yb[2] + S[13] * yb[3] + S[14] * yb[4];
   int i = 0;
 #pragma unroll
   for (int k = 0; k < 5; ++k)
 #pragma unroll
-    for (int j = k; j < 5; ++j, ++i) Sb[i] += (j == k) ? u[k] * x[k] : u[k] * x[j] + u[j] * x[k];
+    for (int j = k; j < 5; ++j, ++i) Sb[i] += (j == k) ? yb[k] * x[k] : yb[k] * x[j] + yb[j] * x[k];
 }
 
-// Reverse of face_side (moment-matrix form).  Adds the cotangents of the
-// side's trace (q, dq) given those of its accumulator contributions.
+// Reverse of face_side (moment-matrix form, slopes times the density).  Adds
+// the cotangents of the side's trace (q, dq) given those of its accumulator
+// contributions.
 template <class T>
 DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const FaceAcc<T>& accb, T qb[5],
                           T dqb[3][5], T sg) {
   const T K = T(ph.K), gm1 = T(ph.gm1), inv_k3 = T(ph.inv_k3);
   const Prim<T> s = primitive(q, gm1);
   const Solver5<T> S(s, K, inv_k3);
-  const T ir = s.ir;
-  T a[3][5], A[5], b[3][5], bA[5], dtq[5];
+  T ra[3][5], rA[5], dtq[5];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) b[i][k] = dq[i][k] * ir;
-    S(b[i], a[i]);
-  }
+  for (int i = 0; i < 3; ++i) S(dq[i], ra[i]);
   euler_dt(s, q, gm1, dq, dtq);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) bA[k] = dtq[k] * ir;
-  S(bA, A);
+  S(dtq, rA);
   T M[7];
   mom_half(s.U, s.th, sg, M);
   const Transverse<T> tr(s.V, s.W, s.th, K);
@@ -604,13 +587,13 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
 #pragma unroll
   for (int n = 0; n < 7; ++n) Mb[n] = T(0);
   TransverseBar<T> trb = transverse_bar_zero<T>();
-  T ab[3][5], Ab[5];
+  T rab[3][5], rAb[5];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) zero5(ab[i]);
-  zero5(Ab);
+  for (int i = 0; i < 3; ++i) zero5(rab[i]);
+  zero5(rAb);
   T rb = T(0);
   T H[15], Hb[15];
-  // <psi psi^T>: Q0 (its first column) and dQ0_i
+  // <psi psi^T>: Q0 (r times its first column) and dQ0_i
   mat_H<0>(M, tr, H);
 #pragma unroll
   for (int k = 0; k < 15; ++k) Hb[k] = T(0);
@@ -620,9 +603,9 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
     Hb[k] += r * accb.Q0[k];
   }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) sym_mv_bwd(H, a[i], r, accb.dQ0[i], Hb, ab[i], rb);
+  for (int i = 0; i < 3; ++i) sym_mv_bwd(H, ra[i], accb.dQ0[i], Hb, rab[i]);
   mat_H_bwd<0>(M, tr, Hb, Mb, trb);
-  // <u psi psi^T>: m4 (first column) and m6
+  // <u psi psi^T>: m4 (r times its first column) and m6
   mat_H<1>(M, tr, H);
 #pragma unroll
   for (int k = 0; k < 15; ++k) Hb[k] = T(0);
@@ -631,54 +614,38 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
     rb += accb.m4[k] * H[k];
     Hb[k] += r * accb.m4[k];
   }
-  sym_mv_bwd(H, A, r, accb.m6, Hb, Ab, rb);
+  sym_mv_bwd(H, rA, accb.m6, Hb, rAb);
   mat_H_bwd<1>(M, tr, Hb, Mb, trb);
-  // m5 = r (<u^2 psi psi^T> a_0 + <u v psi psi^T> a_1 + <u w psi psi^T> a_2)
+  // m5 = <u^2 psi psi^T> ra_0 + <u v psi psi^T> ra_1 + <u w psi psi^T> ra_2
   mat_H<2>(M, tr, H);
 #pragma unroll
   for (int k = 0; k < 15; ++k) Hb[k] = T(0);
-  sym_mv_bwd(H, a[0], r, accb.m5, Hb, ab[0], rb);
+  sym_mv_bwd(H, ra[0], accb.m5, Hb, rab[0]);
   mat_H_bwd<2>(M, tr, Hb, Mb, trb);
   mat_Gv(M, tr, H);
 #pragma unroll
   for (int k = 0; k < 15; ++k) Hb[k] = T(0);
-  sym_mv_bwd(H, a[1], r, accb.m5, Hb, ab[1], rb);
+  sym_mv_bwd(H, ra[1], accb.m5, Hb, rab[1]);
   mat_Gv_bwd(M, tr, Hb, Mb, trb);
   mat_Gw(M, tr, H);
 #pragma unroll
   for (int k = 0; k < 15; ++k) Hb[k] = T(0);
-  sym_mv_bwd(H, a[2], r, accb.m5, Hb, ab[2], rb);
+  sym_mv_bwd(H, ra[2], accb.m5, Hb, rab[2]);
   mat_Gw_bwd(M, tr, Hb, Mb, trb);
 
   Prim<T> sb = prim_zero<T>();
   sb.rho += rb;
   transverse_bwd(tr, s.th, K, trb, sb.V, sb.W, sb.th);
   mom_half_bwd(s.U, s.th, sg, M, Mb, sb.U, sb.th);
-  // time slope A = S(dt/rho), dt = -sum_e J_e dq_e
+  // rA = S(dt), dt = -sum_e J_e dq_e
   Solver5Bar<T> Sb;
-  T bAb[5], dtqb[5];
-  zero5(bAb);
-  solve_bwd(S, bA, A, Ab, bAb, Sb);
-  T irb = T(0);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    dtqb[k] = bAb[k] * ir;
-    irb += bAb[k] * dtq[k];
-  }
+  T dtqb[5];
+  zero5(dtqb);
+  solve_bwd(S, dtq, rA, rAb, dtqb, Sb);
   euler_dt_bwd(s, q, gm1, dq, dtqb, dqb, sb, qb);
-  // slopes a_i = S(dq_i / rho)
+  // ra_i = S(dq_i)
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    T bb[5];
-    zero5(bb);
-    solve_bwd(S, b[i], a[i], ab[i], bb, Sb);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      dqb[i][k] += bb[k] * ir;
-      irb += bb[k] * dq[i][k];
-    }
-  }
-  sb.ir += irb;
+  for (int i = 0; i < 3; ++i) solve_bwd(S, dq[i], ra[i], rab[i], dqb[i], Sb);
   solver_ctor_bwd(S, Sb, K, inv_k3, sb);
   prim_bwd(q, s, sb, gm1, qb);
 }

@@ -444,6 +444,44 @@ DGK_HD void sym_mv_acc(const T S[15], const T x[5], T y[5]) {
   y[4] += S[4] * x[0] + S[8] * x[1] + S[11] * x[2] + S[13] * x[3] + S[14] * x[4];
 }
 
+// m5 += <u psi Phi> with Phi = u (x.psi) + v (y.psi) + w (z.psi), i.e.
+// <u^2 psi psi^T> x + <u v psi psi^T> y + <u w psi psi^T> z without forming the
+// matrices.  Phi = P0 + P1 u + P2 u^2 + P3 u^3 with coefficients polynomial in
+// (v, w, r) (psi_4 = (u^2 + r)/2), and <u^n f(v, w, xi)> = M_n <f>, so
+//   m5_0 = sum_j M_{1+j} <P_j>,      m5_1 = sum_j M_{2+j} <P_j>,
+//   m5_2 = sum_j M_{1+j} <v P_j>,    m5_3 = sum_j M_{1+j} <w P_j>,
+//   m5_4 = sum_j (M_{3+j} <P_j> + M_{1+j} <r P_j>) / 2.
+template <class T>
+DGK_HD void m5_acc(const T* M, const Transverse<T>& t, const T x[5], const T y[5], const T z[5], T m5[5]) {
+  const T hx4 = T(0.5) * x[4], hy4 = T(0.5) * y[4], hz4 = T(0.5) * z[4];
+  const T VW = t.V * t.W, v2W = t.v2 * t.W, Vw2 = t.V * t.w2;
+  // P3 = x4 / 2
+  const T p3 = hx4, vp3 = hx4 * t.V, wp3 = hx4 * t.W, rp3 = hx4 * t.R1;
+  // P2 = x1 + (y4 / 2) v + (z4 / 2) w
+  const T p2 = x[1] + hy4 * t.V + hz4 * t.W;
+  const T vp2 = x[1] * t.V + hy4 * t.v2 + hz4 * VW;
+  const T wp2 = x[1] * t.W + hy4 * VW + hz4 * t.w2;
+  const T rp2 = x[1] * t.R1 + hy4 * t.vr + hz4 * t.wr;
+  // P1 = x0 + (x2 + y1) v + (x3 + z1) w + (x4 / 2) r
+  const T d = x[2] + y[1], e = x[3] + z[1];
+  const T p1 = x[0] + d * t.V + e * t.W + hx4 * t.R1;
+  const T vp1 = x[0] * t.V + d * t.v2 + e * VW + hx4 * t.vr;
+  const T wp1 = x[0] * t.W + d * VW + e * t.w2 + hx4 * t.wr;
+  const T rp1 = x[0] * t.R1 + d * t.vr + e * t.wr + hx4 * t.R2;
+  // P0 = y0 v + z0 w + y2 v^2 + (y3 + z2) v w + z3 w^2 + (y4 / 2) v r + (z4 / 2) w r
+  const T c = y[3] + z[2];
+  const T p0 = y[0] * t.V + z[0] * t.W + y[2] * t.v2 + c * VW + z[3] * t.w2 + hy4 * t.vr + hz4 * t.wr;
+  const T vp0 = y[0] * t.v2 + z[0] * VW + y[2] * t.v3 + c * v2W + z[3] * Vw2 + hy4 * t.v2r + hz4 * t.vwr;
+  const T wp0 = y[0] * VW + z[0] * t.w2 + y[2] * v2W + c * Vw2 + z[3] * t.w3 + hy4 * t.vwr + hz4 * t.w2r;
+  const T rp0 = y[0] * t.vr + z[0] * t.wr + y[2] * t.v2r + c * t.vwr + z[3] * t.w2r + hy4 * t.vr2 + hz4 * t.wr2;
+  m5[0] += M[1] * p0 + M[2] * p1 + M[3] * p2 + M[4] * p3;
+  m5[1] += M[2] * p0 + M[3] * p1 + M[4] * p2 + M[5] * p3;
+  m5[2] += M[1] * vp0 + M[2] * vp1 + M[3] * vp2 + M[4] * vp3;
+  m5[3] += M[1] * wp0 + M[2] * wp1 + M[3] * wp2 + M[4] * wp3;
+  m5[4] += T(0.5) * (M[3] * p0 + M[4] * p1 + M[5] * p2 + M[6] * p3 + M[1] * rp0 + M[2] * rp1 + M[3] * rp2 +
+                     M[4] * rp3);
+}
+
 // sg = +1: lower cell (half space u > 0); sg = -1: upper cell (u < 0).
 template <class T>
 DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>& acc, int& bad, T sg) {
@@ -480,12 +518,8 @@ DGK_HD void face_side(const Phys& ph, const T q[5], const T dq[3][5], FaceAcc<T>
   acc.m4[3] += r * H[3];
   acc.m4[4] += r * H[4];
   sym_mv_acc(H, rA, acc.m6);
-  mat_H<2>(M, tr, H);  // <u^2 psi psi^T>
-  sym_mv_acc(H, ra[0], acc.m5);
-  mat_Gv(M, tr, H);  // <u v psi psi^T>
-  sym_mv_acc(H, ra[1], acc.m5);
-  mat_Gw(M, tr, H);  // <u w psi psi^T>
-  sym_mv_acc(H, ra[2], acc.m5);
+  // <u^2 psi psi^T> ra_0 + <u v psi psi^T> ra_1 + <u w psi psi^T> ra_2
+  m5_acc(M, tr, ra[0], ra[1], ra[2], acc.m5);
 }
 
 // ec: the constants of exp_neg_tab (LDS in the face kernel).

@@ -300,6 +300,42 @@ DGK_HD void euler_dt(const Prim<T>& s, const T Q[5], T gm1, const T dq[3][5], T 
   for (int k = 0; k < 5; ++k) out[k] = -(j0[k] + j1[k] + j2[k]);
 }
 
+// prim_grad and euler_dt of the same (Q, dQ) in one pass, sharing the velocity
+// and pressure derivatives: with t_ej = dQ_e[1+j] - U_j dQ_e[0] = rho dU_j/dx_e,
+//   J_e dQ_e = (dQ_e[1+e],  dQ_e[1+e] U_j + U_e t_ej + delta_je dp/dx_e,
+//               (dQ_e[4] + dp/dx_e) U_e + (rho E + p) dU_e/dx_e),
+// and out = -sum_e J_e dQ_e.
+template <class T>
+DGK_HD Grad<T> prim_grad_dt(const Prim<T>& s, const T Q[5], const T dq[3][5], T gm1, T out[5]) {
+  Grad<T> g;
+  const T ir = s.ir;
+  const T U[3] = {s.U, s.V, s.W};
+  const T ke = T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W);
+  const T Hs = Q[4] + s.p;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    T um = T(0), t[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      t[j] = dq[e][1 + j] - U[j] * dq[e][0];
+      g.dU[e][j] = t[j] * ir;
+      um += U[j] * dq[e][1 + j];
+    }
+    g.dp[e] = gm1 * (dq[e][4] - um + ke * dq[e][0]);
+    g.dT[e] = (g.dp[e] - s.th * dq[e][0]) * ir;
+    const T m = dq[e][1 + e];
+    T jv[5];  // J_e dQ_e
+    jv[0] = m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) jv[1 + j] = m * U[j] + U[e] * t[j];
+    jv[1 + e] += g.dp[e];
+    jv[4] = (dq[e][4] + g.dp[e]) * U[e] + Hs * g.dU[e][e];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) out[k] = (e == 0) ? -jv[k] : out[k] - jv[k];
+  }
+  return g;
+}
+
 // Identity (ii) along axis D, without the factor p.
 template <int D, class T>
 DGK_HD void ns_moment(const Prim<T>& s, const Grad<T>& g, T two_k3, T cp, T out[5]) {
@@ -530,9 +566,8 @@ DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], 
   bad |= int(unphysical(s0));
   T m1[5], m2[5], m3[5], dt0[5];
   euler_flux<0>(s0, acc.Q0, m1);
-  euler_dt(s0, acc.Q0, gm1, acc.dQ0, dt0);  // rho0 <Abar psi>
+  const Grad<T> g = prim_grad_dt(s0, acc.Q0, acc.dQ0, gm1, dt0);  // dt0 = rho0 <Abar psi>
   euler_jvp<0>(s0, acc.Q0, gm1, dt0, m3);
-  const Grad<T> g = prim_grad(s0, acc.dQ0, gm1);
   T ns[5];
   ns_moment<0>(s0, g, T(2.0 * ph.inv_k3), T(ph.cp), ns);  // (m2 + m3) / p0
 #pragma unroll
@@ -583,12 +618,11 @@ DGK_HD void volume_flux(const Phys& ph, const T q[5], const T dq[3][5], T F[3][5
   const Prim<T> s = primitive(q, gm1);
   bad |= int(unphysical(s));
   T dt[5];
-  euler_dt(s, q, gm1, dq, dt);
+  const Grad<T> g = prim_grad_dt(s, q, dq, gm1, dt);
   euler_jvp<0>(s, q, gm1, dt, Ft[0]);
   euler_jvp<1>(s, q, gm1, dt, Ft[1]);
   euler_jvp<2>(s, q, gm1, dt, Ft[2]);
   if constexpr (NEED_F) {
-    const Grad<T> g = prim_grad(s, dq, gm1);
     const T mu = T(ph.mu);
     const T heat = mu * T(ph.inv_pr_m1) * T(ph.cp);  // extra heat-flux factor of 1/Pr - 1
     static_for<3>([&](auto dc) {

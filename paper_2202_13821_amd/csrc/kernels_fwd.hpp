@@ -225,8 +225,9 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
   // The traces on this face depend on a cell's modes only through their
   // values at xi_D = +-1: per side s and variable, the tangential-mode
   // coefficients of the trace, ct[v][t] = sum_{e_D} c[v][n(e_D, t)] P_{e_D}(+-1),
-  // and of its normal derivative, cn[v][t] = sum_{e_D} c[v][n] P'_{e_D}(+-1)
-  // (tangential degree <= K - 1), with P_e(+1) = 1, P_e(-1) = (-1)^e,
+  // and of its normal derivative, cn[v][t] = (2 / h) sum_{e_D} c[v][n] P'_{e_D}(+-1)
+  // with h the side's width along D (tangential degree <= K - 1), with
+  // P_e(+1) = 1, P_e(-1) = (-1)^e,
   // P'_e(+1) = e(e+1)/2, P'_e(-1) = (-1)^(e+1) e(e+1)/2.
   // Side 1 (upper cell) goes to LDS; side 0 (lower cell) keeps its normal-
   // derivative coefficients cn in registers and its trace coefficients ct in
@@ -251,6 +252,17 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
         ct[t] += T(pv) * c;
         if constexpr (ed > 0) cn[t] += T(dv) * c;
       });
+      // the normal derivative in physical units: 2 / (the side's width) once here
+      // rather than at every point
+      {
+        T sn;
+        if constexpr (UNI)
+          sn = T(g.two_inv_h[D]);
+        else
+          sn = sm.st[side][tid];
+#pragma unroll
+        for (int t = 0; t < NT1; ++t) cn[t] *= sn;
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if constexpr (side == 1)
@@ -312,12 +324,11 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
           }
         });
         qs[vl] = v0;
+        dqs[0][vl] = vn;  // cn carries the normal scale
         if constexpr (UNI) {
-          dqs[0][vl] = vn * T(g.two_inv_h[D]);
           dqs[1][vl] = v1 * T(g.two_inv_h[T1]);
           dqs[2][vl] = v2 * T(g.two_inv_h[T2]);
         } else {
-          dqs[0][vl] = vn * sm.st[side][tid];
           dqs[1][vl] = v1 * sm.st[2][tid];
           dqs[2][vl] = v2 * sm.st[3][tid];
         }

@@ -6,8 +6,9 @@ from the kernels' own header and checked against the forms they replace:
   mat_H<2>, mat_Gv and mat_Gw;
 - prim_grad_dt (primitive gradients and the Euler time derivative in one
   pass) against prim_grad and euler_dt;
-- the Solver5 closed form against a dense 5x5 solve of the Maxwellian moment
-  system <a psi psi^T> = b assembled from mat_H<0> over the full line.
+- the Solver5 closed form of <a psi> = b against the Maxwellian moment
+  matrix H = <psi psi^T> assembled by mat_H<0> from the full-line moments (the
+  sum of the two half lines): H S(b) must return b.
 
 Random Maxwellians (both half lines), transverse moments and vectors; the
 forms must agree to a few units of FP64 rounding."""

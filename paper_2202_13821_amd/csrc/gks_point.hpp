@@ -38,8 +38,6 @@ DGK_HD void static_for(F&& f) {
 }
 
 // ---- precision-dispatched math ---------------------------------------------
-DGK_HD float d_erfc(float x) { return erfcf(x); }
-DGK_HD double d_erfc(double x) { return erfc(x); }
 DGK_HD float d_exp(float x) { return expf(x); }
 DGK_HD double d_exp(double x) { return exp(x); }
 DGK_HD float d_sqrt(float x) { return sqrtf(x); }
@@ -103,6 +101,30 @@ DGK_HD bool unphysical(const Prim<T>& s) {
   return !(s.rho > T(0)) || !(s.p > T(0)) || !d_finite(s.U + s.V + s.W + s.p);
 }
 
+// erfc(z) given g = exp(-z^2).  FP32: erfc(|z|) = g t h(t) with t = 1/(1 + |z|/2)
+// and h a degree-10 polynomial fitted to exp(y^2) erfc(y) / t (fit_erfcx.py:
+// relative error 1.2e-8 in exact arithmetic, a few FP32 ulp as evaluated),
+// reflected by erfc(z) = 2 - erfc(-z) for z < 0; the Gaussian is the one the
+// half-space moments need anyway.  FP64: the library erfc.
+DGK_HD float erfc_gauss(float z, float g) {
+#ifdef DGK_FLOPCOUNT
+  (void)g;
+  return erfcf(z);  // counted as one transcendental, like the FP64 library call
+#else
+  constexpr float c[11] = {2.820948064e-01f, 2.820937634e-01f, 2.468845993e-01f, 1.753157228e-01f,
+                           9.346391261e-02f, -5.921645835e-02f, 1.321880221e-01f, -4.549888372e-01f,
+                           4.937071800e-01f, -2.347392291e-01f, 4.319654033e-02f};
+  const float y = fabsf(z);
+  const float t = d_rcp(1.0f + 0.5f * y);
+  float h = c[10];
+#pragma unroll
+  for (int i = 9; i >= 0; --i) h = h * t + c[i];
+  const float r = g * (t * h);
+  return z < 0.0f ? 2.0f - r : r;
+#endif
+}
+DGK_HD double erfc_gauss(double z, double) { return erfc(z); }
+
 // Moments <u^n>, n = 0..6, of the normalised Maxwellian in u over the half
 // line sg u > 0 (sg = +1: u > 0, sg = -1: u < 0): the first two from erfc and
 // the Gaussian at u = 0, then <u^{n+2}> = U <u^{n+1}> + (n+1) th <u^n>
@@ -112,8 +134,9 @@ DGK_HD void mom_half(T U, T th, T sg, T* m) {
   const T r = d_rsqrt(T(2) * th);  // sqrt(lambda)
   const T a = U * r;
   // exp(-lambda U^2) / (2 sqrt(pi lambda)) = exp(-a^2) th r / sqrt(pi)
-  const T e = d_exp_bulk(-a * a) * (th * r * T(0.56418958354775628695));
-  m[0] = T(0.5) * d_erfc(-sg * a);
+  const T ga = d_exp_bulk(-a * a);
+  const T e = ga * (th * r * T(0.56418958354775628695));
+  m[0] = T(0.5) * erfc_gauss(-sg * a, ga);
   m[1] = U * m[0] + sg * e;
 #pragma unroll
   for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + T(n + 1) * th * m[n];

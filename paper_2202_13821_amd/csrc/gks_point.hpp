@@ -641,7 +641,11 @@ DGK_HD void volume_flux(const Phys& ph, const T q[5], const T dq[3][5], T F[3][5
   const Prim<T> s = primitive(q, gm1);
   bad |= int(unphysical(s));
   T dt[5];
-  const Grad<T> g = prim_grad_dt(s, q, dq, gm1, dt);
+  Grad<T> g;  // stage 1 shares the gradients with the time derivative
+  if constexpr (NEED_F)
+    g = prim_grad_dt(s, q, dq, gm1, dt);
+  else
+    euler_dt(s, q, gm1, dq, dt);
   euler_jvp<0>(s, q, gm1, dt, Ft[0]);
   euler_jvp<1>(s, q, gm1, dt, Ft[1]);
   euler_jvp<2>(s, q, gm1, dt, Ft[2]);

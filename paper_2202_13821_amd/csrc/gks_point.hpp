@@ -312,15 +312,60 @@ DGK_HD void euler_jvp(const Prim<T>& s, const T Q[5], T gm1, const T v[5], T out
   out[4] = (v[4] + dp) * Ud + (Q[4] + s.p) * dU[D];
 }
 
-// rho <A psi> = -sum_e J_e(Q) dQ/dx_e
+// out (-)= J_e(Q) dQ_e written out as in euler_jvp, each product subtracted
+// from out as it is formed (assigned when first):
+//   J_e dQ_e = (m, m U_j + U_e t_j + delta_je dp, (dQ_e[4] + dp) U_e + (rho E + p) t_e / rho)
+// with m = dQ_e[1+e], t_j = dQ_e[1+j] - U_j dQ_e[0] and dp the pressure
+// derivative; hi = (rho E + p) / rho.
 template <class T>
-DGK_HD void euler_dt(const Prim<T>& s, const T Q[5], T gm1, const T dq[3][5], T out[5]) {
+DGK_HD void sub_euler_jvp(int e, bool first, const T U[3], T m, const T t[3], T dp, T dq4, T hi, T out[5]) {
+  if (first) {
+    out[0] = -m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) out[1 + j] = -(m * U[j]) - U[e] * t[j];
+    out[4] = -((dq4 + dp) * U[e]) - hi * t[e];
+  } else {
+    out[0] -= m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      out[1 + j] -= m * U[j];
+      out[1 + j] -= U[e] * t[j];
+    }
+    out[4] -= (dq4 + dp) * U[e];
+    out[4] -= hi * t[e];
+  }
+  out[1 + e] -= dp;
+}
+
+// The same as the sum of three euler_jvp: the form of the stage-2 volume flux,
+// whose FP64 P3 kernel spills far less with it.
+template <class T>
+DGK_HD void euler_dt_sum(const Prim<T>& s, const T Q[5], T gm1, const T dq[3][5], T out[5]) {
   T j0[5], j1[5], j2[5];
   euler_jvp<0>(s, Q, gm1, dq[0], j0);
   euler_jvp<1>(s, Q, gm1, dq[1], j1);
   euler_jvp<2>(s, Q, gm1, dq[2], j2);
 #pragma unroll
   for (int k = 0; k < 5; ++k) out[k] = -(j0[k] + j1[k] + j2[k]);
+}
+
+// rho <A psi> = -sum_e J_e(Q) dQ/dx_e
+template <class T>
+DGK_HD void euler_dt(const Prim<T>& s, const T Q[5], T gm1, const T dq[3][5], T out[5]) {
+  const T U[3] = {s.U, s.V, s.W};
+  const T ke = T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W);
+  const T hi = (Q[4] + s.p) * s.ir;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    T um = T(0), t[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      t[j] = dq[e][1 + j] - U[j] * dq[e][0];
+      um += U[j] * dq[e][1 + j];
+    }
+    const T dp = gm1 * (dq[e][4] - um + ke * dq[e][0]);
+    sub_euler_jvp(e, e == 0, U, dq[e][1 + e], t, dp, dq[e][4], hi, out);
+  }
 }
 
 // prim_grad and euler_dt of the same (Q, dQ) in one pass, sharing the velocity
@@ -334,7 +379,7 @@ DGK_HD Grad<T> prim_grad_dt(const Prim<T>& s, const T Q[5], const T dq[3][5], T 
   const T ir = s.ir;
   const T U[3] = {s.U, s.V, s.W};
   const T ke = T(0.5) * (s.U * s.U + s.V * s.V + s.W * s.W);
-  const T Hs = Q[4] + s.p;
+  const T hi = (Q[4] + s.p) * ir;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     T um = T(0), t[3];
@@ -346,15 +391,7 @@ DGK_HD Grad<T> prim_grad_dt(const Prim<T>& s, const T Q[5], const T dq[3][5], T 
     }
     g.dp[e] = gm1 * (dq[e][4] - um + ke * dq[e][0]);
     g.dT[e] = (g.dp[e] - s.th * dq[e][0]) * ir;
-    const T m = dq[e][1 + e];
-    T jv[5];  // J_e dQ_e
-    jv[0] = m;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) jv[1 + j] = m * U[j] + U[e] * t[j];
-    jv[1 + e] += g.dp[e];
-    jv[4] = (dq[e][4] + g.dp[e]) * U[e] + Hs * g.dU[e][e];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) out[k] = (e == 0) ? -jv[k] : out[k] - jv[k];
+    sub_euler_jvp(e, e == 0, U, dq[e][1 + e], t, g.dp[e], dq[e][4], hi, out);
   }
   return g;
 }
@@ -493,14 +530,15 @@ DGK_HD void mat_Gw(const T* M, const Transverse<T>& t, T G[15]) {
   G[14] = T(0.25) * (t.W * M[5] + T(2) * t.wr * M[3] + t.wr2 * M[1]);
 }
 
-// y += S x for a symmetric S stored as above
+// y += S x for a symmetric S stored as above, accumulated onto y one product
+// at a time (one FMA per entry)
 template <class T>
 DGK_HD void sym_mv_acc(const T S[15], const T x[5], T y[5]) {
-  y[0] += S[0] * x[0] + S[1] * x[1] + S[2] * x[2] + S[3] * x[3] + S[4] * x[4];
-  y[1] += S[1] * x[0] + S[5] * x[1] + S[6] * x[2] + S[7] * x[3] + S[8] * x[4];
-  y[2] += S[2] * x[0] + S[6] * x[1] + S[9] * x[2] + S[10] * x[3] + S[11] * x[4];
-  y[3] += S[3] * x[0] + S[7] * x[1] + S[10] * x[2] + S[12] * x[3] + S[13] * x[4];
-  y[4] += S[4] * x[0] + S[8] * x[1] + S[11] * x[2] + S[13] * x[3] + S[14] * x[4];
+  constexpr int e[5][5] = {{0, 1, 2, 3, 4}, {1, 5, 6, 7, 8}, {2, 6, 9, 10, 11}, {3, 7, 10, 12, 13}, {4, 8, 11, 13, 14}};
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) y[k] += S[e[k][j]] * x[j];
 }
 
 // m5 += <u psi Phi> with Phi = u (x.psi) + v (y.psi) + w (z.psi), i.e.
@@ -533,12 +571,20 @@ DGK_HD void m5_acc(const T* M, const Transverse<T>& t, const T x[5], const T y[5
   const T vp0 = y[0] * t.v2 + z[0] * VW + y[2] * t.v3 + c * v2W + z[3] * Vw2 + hy4 * t.v2r + hz4 * t.vwr;
   const T wp0 = y[0] * VW + z[0] * t.w2 + y[2] * v2W + c * Vw2 + z[3] * t.w3 + hy4 * t.vwr + hz4 * t.w2r;
   const T rp0 = y[0] * t.vr + z[0] * t.wr + y[2] * t.v2r + c * t.vwr + z[3] * t.w2r + hy4 * t.vr2 + hz4 * t.wr2;
-  m5[0] += M[1] * p0 + M[2] * p1 + M[3] * p2 + M[4] * p3;
-  m5[1] += M[2] * p0 + M[3] * p1 + M[4] * p2 + M[5] * p3;
-  m5[2] += M[1] * vp0 + M[2] * vp1 + M[3] * vp2 + M[4] * vp3;
-  m5[3] += M[1] * wp0 + M[2] * wp1 + M[3] * wp2 + M[4] * wp3;
-  m5[4] += T(0.5) * (M[3] * p0 + M[4] * p1 + M[5] * p2 + M[6] * p3 + M[1] * rp0 + M[2] * rp1 + M[3] * rp2 +
-                     M[4] * rp3);
+  // accumulated onto m5 one product at a time
+  const T P[4] = {p0, p1, p2, p3}, VP[4] = {vp0, vp1, vp2, vp3}, WP[4] = {wp0, wp1, wp2, wp3};
+  const T RP[4] = {rp0, rp1, rp2, rp3};
+  T s4 = M[3] * p0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    m5[0] += M[1 + j] * P[j];
+    m5[1] += M[2 + j] * P[j];
+    m5[2] += M[1 + j] * VP[j];
+    m5[3] += M[1 + j] * WP[j];
+    if (j > 0) s4 += M[3 + j] * P[j];
+    s4 += M[1 + j] * RP[j];
+  }
+  m5[4] += T(0.5) * s4;
 }
 
 // sg = +1: lower cell (half space u > 0); sg = -1: upper cell (u < 0).
@@ -645,7 +691,7 @@ DGK_HD void volume_flux(const Phys& ph, const T q[5], const T dq[3][5], T F[3][5
   if constexpr (NEED_F)
     g = prim_grad_dt(s, q, dq, gm1, dt);
   else
-    euler_dt(s, q, gm1, dq, dt);
+    euler_dt_sum(s, q, gm1, dq, dt);
   euler_jvp<0>(s, q, gm1, dt, Ft[0]);
   euler_jvp<1>(s, q, gm1, dt, Ft[1]);
   euler_jvp<2>(s, q, gm1, dt, Ft[2]);

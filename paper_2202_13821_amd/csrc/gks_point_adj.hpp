@@ -46,7 +46,9 @@ DGK_HD void prim_bwd(const T Q[5], const Prim<T>& s, Prim<T> sb, T gm1, T Qb[5])
   Qb[1] += sb.U * s.ir;
   Qb[2] += sb.V * s.ir;
   Qb[3] += sb.W * s.ir;
-  sb.ir += sb.U * Q[1] + sb.V * Q[2] + sb.W * Q[3];
+  sb.ir += sb.U * Q[1];
+  sb.ir += sb.V * Q[2];
+  sb.ir += sb.W * Q[3];
   // ir = 1/Q0, rho = Q0
   Qb[0] += sb.rho - sb.ir * s.ir * s.ir;
 }
@@ -115,7 +117,9 @@ DGK_HD void solve_bwd(const Solver5<T>& S, const T b[5], const T a[5], const T a
   ab[4] -= S.E * ab[0];
   // a_i = R_i ith - U_i a4
   T R1b = ab[1] * S.ith, R2b = ab[2] * S.ith, R3b = ab[3] * S.ith;
-  Sb.ith += ab[1] * R1 + ab[2] * R2 + ab[3] * R3;
+  Sb.ith += ab[1] * R1;
+  Sb.ith += ab[2] * R2;
+  Sb.ith += ab[3] * R3;
   Sb.U -= ab[1] * a[4];
   Sb.V -= ab[2] * a[4];
   Sb.W -= ab[3] * a[4];
@@ -147,9 +151,12 @@ DGK_HD void solve_bwd(const Solver5<T>& S, const T b[5], const T a[5], const T a
 template <class T>
 DGK_HD void solver_ctor_bwd(const Solver5<T>& S, const Solver5Bar<T>& Sb, T K, T inv_k3, Prim<T>& sb) {
   T ithb = Sb.ith + Sb.c4 * T(4) * S.ith * inv_k3;
-  sb.U += Sb.U + Sb.E * S.U;
-  sb.V += Sb.V + Sb.E * S.V;
-  sb.W += Sb.W + Sb.E * S.W;
+  sb.U += Sb.U;
+  sb.U += Sb.E * S.U;
+  sb.V += Sb.V;
+  sb.V += Sb.E * S.V;
+  sb.W += Sb.W;
+  sb.W += Sb.E * S.W;
   sb.th += Sb.E * T(0.5) * (K + T(3)) - ithb * S.ith * S.ith;
 }
 
@@ -165,7 +172,8 @@ DGK_HD void euler_flux_bwd(const Prim<T>& s, const T Q[5], const T Fb[5], Prim<T
     Qb[1 + j] += Fb[1 + j] * Ud;
     udb += Fb[1 + j] * Q[1 + j];
   }
-  sb.p += Fb[1 + D] + Fb[4] * Ud;
+  sb.p += Fb[1 + D];
+  sb.p += Fb[4] * Ud;
   Qb[4] += Fb[4] * Ud;
   udb += Fb[4] * (Q[4] + s.p);
   if constexpr (D == 0) sb.U += udb;
@@ -215,7 +223,8 @@ DGK_HD void euler_jvp_bwd(const Prim<T>& s, const T Q[5], T gm1, const T v[5], c
   vb[0] += dpb * gm1 * kk;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    Ub[j] += kkb * U[j] + umb * v[1 + j];
+    Ub[j] += kkb * U[j];
+    Ub[j] += umb * v[1 + j];
     vb[1 + j] += umb * U[j];
   }
   // dU_D = (v_{1+D} - U_D v0) ir
@@ -474,29 +483,68 @@ DGK_HD void transverse_bwd(const Transverse<T>& t, T th, T K, const TransverseBa
   bv4 += b.R2;
   bw4 += b.R2;
   bs2 += b.R2;
-  bv2 += (T(2) * w2 + T(2) * s1) * b.R2 + b.R1;
-  bw2 += (T(2) * v2 + T(2) * s1) * b.R2 + b.R1;
-  bs1 += T(2) * (v2 + w2) * b.R2 + b.R1;
+  bv2 += (T(2) * w2 + T(2) * s1) * b.R2;
+  bv2 += b.R1;
+  bw2 += (T(2) * v2 + T(2) * s1) * b.R2;
+  bw2 += b.R1;
+  bs1 += T(2) * (v2 + w2) * b.R2;
+  bs1 += b.R1;
   // the one-dimensional moments
-  Vb += bV + T(2) * V * bv2 + T(3) * v2 * bv3 + T(4) * v3 * bv4 + T(5) * v4 * bv5;
-  Wb += bW + T(2) * W * bw2 + T(3) * w2 * bw3 + T(4) * w3 * bw4 + T(5) * w4 * bw5;
-  thb += bv2 + T(3) * V * bv3 + T(6) * v2 * bv4 + T(10) * v3 * bv5;
-  thb += bw2 + T(3) * W * bw3 + T(6) * w2 * bw4 + T(10) * w3 * bw5;
-  thb += K * bs1 + T(2) * K * (K + T(2)) * th * bs2;
+  Vb += bV;
+  Vb += T(2) * V * bv2;
+  Vb += T(3) * v2 * bv3;
+  Vb += T(4) * v3 * bv4;
+  Vb += T(5) * v4 * bv5;
+  Wb += bW;
+  Wb += T(2) * W * bw2;
+  Wb += T(3) * w2 * bw3;
+  Wb += T(4) * w3 * bw4;
+  Wb += T(5) * w4 * bw5;
+  thb += bv2;
+  thb += T(3) * V * bv3;
+  thb += T(6) * v2 * bv4;
+  thb += T(10) * v3 * bv5;
+  thb += bw2;
+  thb += T(3) * W * bw3;
+  thb += T(6) * w2 * bw4;
+  thb += T(10) * w3 * bw5;
+  thb += K * bs1;
+  thb += T(2) * K * (K + T(2)) * th * bs2;
 }
 
 // Reverse of mat_H<P>: add the cotangents of M[P..P+4] and of the members.
 template <int P, class T>
 DGK_HD void mat_H_bwd(const T* M, const Transverse<T>& t, const T Hb[15], T* Mb, TransverseBar<T>& tb) {
   const T h = T(0.5), q = T(0.25);
-  Mb[P] += Hb[0] + t.V * Hb[2] + t.W * Hb[3] + h * t.R1 * Hb[4] + t.v2 * Hb[9] + t.V * t.W * Hb[10] +
-           h * t.vr * Hb[11] + t.w2 * Hb[12] + h * t.wr * Hb[13] + q * t.R2 * Hb[14];
-  Mb[P + 1] += Hb[1] + t.V * Hb[6] + t.W * Hb[7] + h * t.R1 * Hb[8];
-  Mb[P + 2] += h * Hb[4] + Hb[5] + h * t.V * Hb[11] + h * t.W * Hb[13] + h * t.R1 * Hb[14];
+  Mb[P] += Hb[0];
+  Mb[P] += t.V * Hb[2];
+  Mb[P] += t.W * Hb[3];
+  Mb[P] += h * t.R1 * Hb[4];
+  Mb[P] += t.v2 * Hb[9];
+  Mb[P] += t.V * t.W * Hb[10];
+  Mb[P] += h * t.vr * Hb[11];
+  Mb[P] += t.w2 * Hb[12];
+  Mb[P] += h * t.wr * Hb[13];
+  Mb[P] += q * t.R2 * Hb[14];
+  Mb[P + 1] += Hb[1];
+  Mb[P + 1] += t.V * Hb[6];
+  Mb[P + 1] += t.W * Hb[7];
+  Mb[P + 1] += h * t.R1 * Hb[8];
+  Mb[P + 2] += h * Hb[4];
+  Mb[P + 2] += Hb[5];
+  Mb[P + 2] += h * t.V * Hb[11];
+  Mb[P + 2] += h * t.W * Hb[13];
+  Mb[P + 2] += h * t.R1 * Hb[14];
   Mb[P + 3] += h * Hb[8];
   Mb[P + 4] += q * Hb[14];
-  tb.V += M[P] * Hb[2] + M[P + 1] * Hb[6] + t.W * M[P] * Hb[10] + h * M[P + 2] * Hb[11];
-  tb.W += M[P] * Hb[3] + M[P + 1] * Hb[7] + t.V * M[P] * Hb[10] + h * M[P + 2] * Hb[13];
+  tb.V += M[P] * Hb[2];
+  tb.V += M[P + 1] * Hb[6];
+  tb.V += t.W * M[P] * Hb[10];
+  tb.V += h * M[P + 2] * Hb[11];
+  tb.W += M[P] * Hb[3];
+  tb.W += M[P + 1] * Hb[7];
+  tb.W += t.V * M[P] * Hb[10];
+  tb.W += h * M[P + 2] * Hb[13];
   tb.R1 += h * (M[P] * Hb[4] + M[P + 1] * Hb[8] + M[P + 2] * Hb[14]);
   tb.v2 += M[P] * Hb[9];
   tb.w2 += M[P] * Hb[12];
@@ -508,16 +556,45 @@ DGK_HD void mat_H_bwd(const T* M, const Transverse<T>& t, const T Hb[15], T* Mb,
 template <class T>
 DGK_HD void mat_Gv_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb, TransverseBar<T>& tb) {
   const T h = T(0.5), q = T(0.25), VW = t.V * t.W;
-  Mb[1] += t.V * Gb[0] + t.v2 * Gb[2] + VW * Gb[3] + h * t.vr * Gb[4] + t.v3 * Gb[9] + t.v2 * t.W * Gb[10] +
-           h * t.v2r * Gb[11] + t.V * t.w2 * Gb[12] + h * t.vwr * Gb[13] + q * t.vr2 * Gb[14];
-  Mb[2] += t.V * Gb[1] + t.v2 * Gb[6] + VW * Gb[7] + h * t.vr * Gb[8];
-  Mb[3] += h * t.V * Gb[4] + t.V * Gb[5] + h * t.v2 * Gb[11] + h * VW * Gb[13] + h * t.vr * Gb[14];
+  Mb[1] += t.V * Gb[0];
+  Mb[1] += t.v2 * Gb[2];
+  Mb[1] += VW * Gb[3];
+  Mb[1] += h * t.vr * Gb[4];
+  Mb[1] += t.v3 * Gb[9];
+  Mb[1] += t.v2 * t.W * Gb[10];
+  Mb[1] += h * t.v2r * Gb[11];
+  Mb[1] += t.V * t.w2 * Gb[12];
+  Mb[1] += h * t.vwr * Gb[13];
+  Mb[1] += q * t.vr2 * Gb[14];
+  Mb[2] += t.V * Gb[1];
+  Mb[2] += t.v2 * Gb[6];
+  Mb[2] += VW * Gb[7];
+  Mb[2] += h * t.vr * Gb[8];
+  Mb[3] += h * t.V * Gb[4];
+  Mb[3] += t.V * Gb[5];
+  Mb[3] += h * t.v2 * Gb[11];
+  Mb[3] += h * VW * Gb[13];
+  Mb[3] += h * t.vr * Gb[14];
   Mb[4] += h * t.V * Gb[8];
   Mb[5] += q * t.V * Gb[14];
-  tb.V += M[1] * Gb[0] + M[2] * Gb[1] + t.W * M[1] * Gb[3] + h * M[3] * Gb[4] + M[3] * Gb[5] + t.W * M[2] * Gb[7] +
-          h * M[4] * Gb[8] + t.w2 * M[1] * Gb[12] + h * t.W * M[3] * Gb[13] + q * M[5] * Gb[14];
-  tb.W += t.V * M[1] * Gb[3] + t.V * M[2] * Gb[7] + t.v2 * M[1] * Gb[10] + h * t.V * M[3] * Gb[13];
-  tb.v2 += M[1] * Gb[2] + M[2] * Gb[6] + t.W * M[1] * Gb[10] + h * M[3] * Gb[11];
+  tb.V += M[1] * Gb[0];
+  tb.V += M[2] * Gb[1];
+  tb.V += t.W * M[1] * Gb[3];
+  tb.V += h * M[3] * Gb[4];
+  tb.V += M[3] * Gb[5];
+  tb.V += t.W * M[2] * Gb[7];
+  tb.V += h * M[4] * Gb[8];
+  tb.V += t.w2 * M[1] * Gb[12];
+  tb.V += h * t.W * M[3] * Gb[13];
+  tb.V += q * M[5] * Gb[14];
+  tb.W += t.V * M[1] * Gb[3];
+  tb.W += t.V * M[2] * Gb[7];
+  tb.W += t.v2 * M[1] * Gb[10];
+  tb.W += h * t.V * M[3] * Gb[13];
+  tb.v2 += M[1] * Gb[2];
+  tb.v2 += M[2] * Gb[6];
+  tb.v2 += t.W * M[1] * Gb[10];
+  tb.v2 += h * M[3] * Gb[11];
   tb.vr += h * (M[1] * Gb[4] + M[2] * Gb[8] + M[3] * Gb[14]);
   tb.v3 += M[1] * Gb[9];
   tb.v2r += h * M[1] * Gb[11];
@@ -529,16 +606,45 @@ DGK_HD void mat_Gv_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb
 template <class T>
 DGK_HD void mat_Gw_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb, TransverseBar<T>& tb) {
   const T h = T(0.5), q = T(0.25), VW = t.V * t.W;
-  Mb[1] += t.W * Gb[0] + VW * Gb[2] + t.w2 * Gb[3] + h * t.wr * Gb[4] + t.W * t.v2 * Gb[9] + t.V * t.w2 * Gb[10] +
-           h * t.vwr * Gb[11] + t.w3 * Gb[12] + h * t.w2r * Gb[13] + q * t.wr2 * Gb[14];
-  Mb[2] += t.W * Gb[1] + VW * Gb[6] + t.w2 * Gb[7] + h * t.wr * Gb[8];
-  Mb[3] += h * t.W * Gb[4] + t.W * Gb[5] + h * VW * Gb[11] + h * t.w2 * Gb[13] + h * t.wr * Gb[14];
+  Mb[1] += t.W * Gb[0];
+  Mb[1] += VW * Gb[2];
+  Mb[1] += t.w2 * Gb[3];
+  Mb[1] += h * t.wr * Gb[4];
+  Mb[1] += t.W * t.v2 * Gb[9];
+  Mb[1] += t.V * t.w2 * Gb[10];
+  Mb[1] += h * t.vwr * Gb[11];
+  Mb[1] += t.w3 * Gb[12];
+  Mb[1] += h * t.w2r * Gb[13];
+  Mb[1] += q * t.wr2 * Gb[14];
+  Mb[2] += t.W * Gb[1];
+  Mb[2] += VW * Gb[6];
+  Mb[2] += t.w2 * Gb[7];
+  Mb[2] += h * t.wr * Gb[8];
+  Mb[3] += h * t.W * Gb[4];
+  Mb[3] += t.W * Gb[5];
+  Mb[3] += h * VW * Gb[11];
+  Mb[3] += h * t.w2 * Gb[13];
+  Mb[3] += h * t.wr * Gb[14];
   Mb[4] += h * t.W * Gb[8];
   Mb[5] += q * t.W * Gb[14];
-  tb.W += M[1] * Gb[0] + M[2] * Gb[1] + t.V * M[1] * Gb[2] + h * M[3] * Gb[4] + M[3] * Gb[5] + t.V * M[2] * Gb[6] +
-          h * M[4] * Gb[8] + t.v2 * M[1] * Gb[9] + h * t.V * M[3] * Gb[11] + q * M[5] * Gb[14];
-  tb.V += t.W * M[1] * Gb[2] + t.W * M[2] * Gb[6] + t.w2 * M[1] * Gb[10] + h * t.W * M[3] * Gb[11];
-  tb.w2 += M[1] * Gb[3] + M[2] * Gb[7] + t.V * M[1] * Gb[10] + h * M[3] * Gb[13];
+  tb.W += M[1] * Gb[0];
+  tb.W += M[2] * Gb[1];
+  tb.W += t.V * M[1] * Gb[2];
+  tb.W += h * M[3] * Gb[4];
+  tb.W += M[3] * Gb[5];
+  tb.W += t.V * M[2] * Gb[6];
+  tb.W += h * M[4] * Gb[8];
+  tb.W += t.v2 * M[1] * Gb[9];
+  tb.W += h * t.V * M[3] * Gb[11];
+  tb.W += q * M[5] * Gb[14];
+  tb.V += t.W * M[1] * Gb[2];
+  tb.V += t.W * M[2] * Gb[6];
+  tb.V += t.w2 * M[1] * Gb[10];
+  tb.V += h * t.W * M[3] * Gb[11];
+  tb.w2 += M[1] * Gb[3];
+  tb.w2 += M[2] * Gb[7];
+  tb.w2 += t.V * M[1] * Gb[10];
+  tb.w2 += h * M[3] * Gb[13];
   tb.wr += h * (M[1] * Gb[4] + M[2] * Gb[8] + M[3] * Gb[14]);
   tb.v2 += t.W * M[1] * Gb[9];
   tb.vwr += h * M[1] * Gb[11];
@@ -552,16 +658,20 @@ DGK_HD void mat_Gw_bwd(const T* M, const Transverse<T>& t, const T Gb[15], T* Mb
 // (k < j), Sbar_kk += ybar_k x_k.
 template <class T>
 DGK_HD void sym_mv_bwd(const T S[15], const T x[5], const T yb[5], T Sb[15], T xb[5]) {
-  xb[0] += S[0] * yb[0] + S[1] * yb[1] + S[2] * yb[2] + S[3] * yb[3] + S[4] * yb[4];
-  xb[1] += S[1] * yb[0] + S[5] * yb[1] + S[6] * yb[2] + S[7] * yb[3] + S[8] * yb[4];
-  xb[2] += S[2] * yb[0] + S[6] * yb[1] + S[9] * yb[2] + S[10] * yb[3] + S[11] * yb[4];
-  xb[3] += S[3] * yb[0] + S[7] * yb[1] + S[10] * yb[2] + S[12] * yb[3] + S[13] * yb[4];
-  xb[4] += S[4] * yb[0] + S[8] * yb[1] + S[11] * yb[2] + S[13] * yb[3] + S[14] * yb[4];
+  // accumulated one product at a time (one FMA each)
+  constexpr int e[5][5] = {{0, 1, 2, 3, 4}, {1, 5, 6, 7, 8}, {2, 6, 9, 10, 11}, {3, 7, 10, 12, 13}, {4, 8, 11, 13, 14}};
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) xb[k] += S[e[k][j]] * yb[j];
   int i = 0;
 #pragma unroll
   for (int k = 0; k < 5; ++k)
 #pragma unroll
-    for (int j = k; j < 5; ++j, ++i) Sb[i] += (j == k) ? yb[k] * x[k] : yb[k] * x[j] + yb[j] * x[k];
+    for (int j = k; j < 5; ++j, ++i) {
+      Sb[i] += yb[k] * x[j];
+      if (j != k) Sb[i] += yb[j] * x[k];
+    }
 }
 
 // Reverse of face_side (moment-matrix form, slopes times the density).  Adds

@@ -674,6 +674,182 @@ DGK_HD void sym_mv_bwd(const T S[15], const T x[5], const T yb[5], T Sb[15], T x
     }
 }
 
+// Reverse of m5_acc (gks_point.hpp): given the cotangent ob of m5, adds the
+// cotangents of M[1..6], of the transverse moments and of x, y, z.  Each line
+// reverses one product of the forward, in the forward's grouping P3, P2, P1, P0.
+template <class T>
+DGK_HD void m5_acc_bwd(const T* M, const Transverse<T>& t, const T x[5], const T y[5], const T z[5], const T ob[5],
+                       T* Mb, TransverseBar<T>& tb, T xb[5], T yb[5], T zb[5]) {
+  // forward values
+  const T hx4 = T(0.5) * x[4], hy4 = T(0.5) * y[4], hz4 = T(0.5) * z[4];
+  const T VW = t.V * t.W, v2W = t.v2 * t.W, Vw2 = t.V * t.w2;
+  const T d = x[2] + y[1], e = x[3] + z[1], c = y[3] + z[2];
+  const T P[4] = {y[0] * t.V + z[0] * t.W + y[2] * t.v2 + c * VW + z[3] * t.w2 + hy4 * t.vr + hz4 * t.wr,
+                  x[0] + d * t.V + e * t.W + hx4 * t.R1, x[1] + hy4 * t.V + hz4 * t.W, hx4};
+  const T VP[4] = {y[0] * t.v2 + z[0] * VW + y[2] * t.v3 + c * v2W + z[3] * Vw2 + hy4 * t.v2r + hz4 * t.vwr,
+                   x[0] * t.V + d * t.v2 + e * VW + hx4 * t.vr, x[1] * t.V + hy4 * t.v2 + hz4 * VW, hx4 * t.V};
+  const T WP[4] = {y[0] * VW + z[0] * t.w2 + y[2] * v2W + c * Vw2 + z[3] * t.w3 + hy4 * t.vwr + hz4 * t.w2r,
+                   x[0] * t.W + d * VW + e * t.w2 + hx4 * t.wr, x[1] * t.W + hy4 * VW + hz4 * t.w2, hx4 * t.W};
+  const T RP[4] = {y[0] * t.vr + z[0] * t.wr + y[2] * t.v2r + c * t.vwr + z[3] * t.w2r + hy4 * t.vr2 + hz4 * t.wr2,
+                   x[0] * t.R1 + d * t.vr + e * t.wr + hx4 * t.R2, x[1] * t.R1 + hy4 * t.vr + hz4 * t.wr, hx4 * t.R1};
+  // the moment sums
+  const T h4 = T(0.5) * ob[4];
+  T Pb[4], VPb[4], WPb[4], RPb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    Pb[j] = M[1 + j] * ob[0];
+    Pb[j] += M[2 + j] * ob[1];
+    Pb[j] += M[3 + j] * h4;
+    VPb[j] = M[1 + j] * ob[2];
+    WPb[j] = M[1 + j] * ob[3];
+    RPb[j] = M[1 + j] * h4;
+    Mb[1 + j] += ob[0] * P[j];
+    Mb[1 + j] += ob[2] * VP[j];
+    Mb[1 + j] += ob[3] * WP[j];
+    Mb[1 + j] += h4 * RP[j];
+    Mb[2 + j] += ob[1] * P[j];
+    Mb[3 + j] += h4 * P[j];
+  }
+  T hx4b = T(0), hy4b = T(0), hz4b = T(0), db = T(0), eb = T(0), cb = T(0), VWb = T(0), v2Wb = T(0), Vw2b = T(0);
+  // P3 = hx4, vP3 = hx4 V, wP3 = hx4 W, rP3 = hx4 R1
+  hx4b += Pb[3];
+  hx4b += VPb[3] * t.V;
+  tb.V += VPb[3] * hx4;
+  hx4b += WPb[3] * t.W;
+  tb.W += WPb[3] * hx4;
+  hx4b += RPb[3] * t.R1;
+  tb.R1 += RPb[3] * hx4;
+  // P2 = x1 + hy4 V + hz4 W and its v, w, r moments
+  xb[1] += Pb[2];
+  hy4b += Pb[2] * t.V;
+  tb.V += Pb[2] * hy4;
+  hz4b += Pb[2] * t.W;
+  tb.W += Pb[2] * hz4;
+  xb[1] += VPb[2] * t.V;
+  tb.V += VPb[2] * x[1];
+  hy4b += VPb[2] * t.v2;
+  tb.v2 += VPb[2] * hy4;
+  hz4b += VPb[2] * VW;
+  VWb += VPb[2] * hz4;
+  xb[1] += WPb[2] * t.W;
+  tb.W += WPb[2] * x[1];
+  hy4b += WPb[2] * VW;
+  VWb += WPb[2] * hy4;
+  hz4b += WPb[2] * t.w2;
+  tb.w2 += WPb[2] * hz4;
+  xb[1] += RPb[2] * t.R1;
+  tb.R1 += RPb[2] * x[1];
+  hy4b += RPb[2] * t.vr;
+  tb.vr += RPb[2] * hy4;
+  hz4b += RPb[2] * t.wr;
+  tb.wr += RPb[2] * hz4;
+  // P1 = x0 + d V + e W + hx4 R1 and its v, w, r moments
+  xb[0] += Pb[1];
+  db += Pb[1] * t.V;
+  tb.V += Pb[1] * d;
+  eb += Pb[1] * t.W;
+  tb.W += Pb[1] * e;
+  hx4b += Pb[1] * t.R1;
+  tb.R1 += Pb[1] * hx4;
+  xb[0] += VPb[1] * t.V;
+  tb.V += VPb[1] * x[0];
+  db += VPb[1] * t.v2;
+  tb.v2 += VPb[1] * d;
+  eb += VPb[1] * VW;
+  VWb += VPb[1] * e;
+  hx4b += VPb[1] * t.vr;
+  tb.vr += VPb[1] * hx4;
+  xb[0] += WPb[1] * t.W;
+  tb.W += WPb[1] * x[0];
+  db += WPb[1] * VW;
+  VWb += WPb[1] * d;
+  eb += WPb[1] * t.w2;
+  tb.w2 += WPb[1] * e;
+  hx4b += WPb[1] * t.wr;
+  tb.wr += WPb[1] * hx4;
+  xb[0] += RPb[1] * t.R1;
+  tb.R1 += RPb[1] * x[0];
+  db += RPb[1] * t.vr;
+  tb.vr += RPb[1] * d;
+  eb += RPb[1] * t.wr;
+  tb.wr += RPb[1] * e;
+  hx4b += RPb[1] * t.R2;
+  tb.R2 += RPb[1] * hx4;
+  // P0 = y0 V + z0 W + y2 v^2 + c VW + z3 w^2 + hy4 v r + hz4 w r and its v, w, r moments
+  yb[0] += Pb[0] * t.V;
+  tb.V += Pb[0] * y[0];
+  zb[0] += Pb[0] * t.W;
+  tb.W += Pb[0] * z[0];
+  yb[2] += Pb[0] * t.v2;
+  tb.v2 += Pb[0] * y[2];
+  cb += Pb[0] * VW;
+  VWb += Pb[0] * c;
+  zb[3] += Pb[0] * t.w2;
+  tb.w2 += Pb[0] * z[3];
+  hy4b += Pb[0] * t.vr;
+  tb.vr += Pb[0] * hy4;
+  hz4b += Pb[0] * t.wr;
+  tb.wr += Pb[0] * hz4;
+  yb[0] += VPb[0] * t.v2;
+  tb.v2 += VPb[0] * y[0];
+  zb[0] += VPb[0] * VW;
+  VWb += VPb[0] * z[0];
+  yb[2] += VPb[0] * t.v3;
+  tb.v3 += VPb[0] * y[2];
+  cb += VPb[0] * v2W;
+  v2Wb += VPb[0] * c;
+  zb[3] += VPb[0] * Vw2;
+  Vw2b += VPb[0] * z[3];
+  hy4b += VPb[0] * t.v2r;
+  tb.v2r += VPb[0] * hy4;
+  hz4b += VPb[0] * t.vwr;
+  tb.vwr += VPb[0] * hz4;
+  yb[0] += WPb[0] * VW;
+  VWb += WPb[0] * y[0];
+  zb[0] += WPb[0] * t.w2;
+  tb.w2 += WPb[0] * z[0];
+  yb[2] += WPb[0] * v2W;
+  v2Wb += WPb[0] * y[2];
+  cb += WPb[0] * Vw2;
+  Vw2b += WPb[0] * c;
+  zb[3] += WPb[0] * t.w3;
+  tb.w3 += WPb[0] * z[3];
+  hy4b += WPb[0] * t.vwr;
+  tb.vwr += WPb[0] * hy4;
+  hz4b += WPb[0] * t.w2r;
+  tb.w2r += WPb[0] * hz4;
+  yb[0] += RPb[0] * t.vr;
+  tb.vr += RPb[0] * y[0];
+  zb[0] += RPb[0] * t.wr;
+  tb.wr += RPb[0] * z[0];
+  yb[2] += RPb[0] * t.v2r;
+  tb.v2r += RPb[0] * y[2];
+  cb += RPb[0] * t.vwr;
+  tb.vwr += RPb[0] * c;
+  zb[3] += RPb[0] * t.w2r;
+  tb.w2r += RPb[0] * z[3];
+  hy4b += RPb[0] * t.vr2;
+  tb.vr2 += RPb[0] * hy4;
+  hz4b += RPb[0] * t.wr2;
+  tb.wr2 += RPb[0] * hz4;
+  // d = x2 + y1, e = x3 + z1, c = y3 + z2, the halves and the products of members
+  xb[2] += db;
+  yb[1] += db;
+  xb[3] += eb;
+  zb[1] += eb;
+  yb[3] += cb;
+  zb[2] += cb;
+  xb[4] += T(0.5) * hx4b;
+  yb[4] += T(0.5) * hy4b;
+  zb[4] += T(0.5) * hz4b;
+  tb.V += VWb * t.W;
+  tb.W += VWb * t.V;
+  tb.v2 += v2Wb * t.W;
+  tb.W += v2Wb * t.v2;
+  tb.V += Vw2b * t.w2;
+  tb.w2 += Vw2b * t.V;
+}
+
 // Reverse of face_side (moment-matrix form, slopes times the density).  Adds
 // the cotangents of the side's trace (q, dq) given those of its accumulator
 // contributions.
@@ -726,22 +902,28 @@ DGK_HD void face_side_vjp(const Phys& ph, const T q[5], const T dq[3][5], const 
   }
   sym_mv_bwd(H, rA, accb.m6, Hb, rAb);
   mat_H_bwd<1>(M, tr, Hb, Mb, trb);
-  // m5 = <u^2 psi psi^T> ra_0 + <u v psi psi^T> ra_1 + <u w psi psi^T> ra_2
-  mat_H<2>(M, tr, H);
+  // m5 = <u^2 psi psi^T> ra_0 + <u v psi psi^T> ra_1 + <u w psi psi^T> ra_2: the
+  // matrix-free reverse in FP32; the FP64 lanes, which spill, run faster with
+  // the matrices (5.8% on the FP64 P2 adjoint)
+  if constexpr (sizeof(T) == 4) {
+    m5_acc_bwd(M, tr, ra[0], ra[1], ra[2], accb.m5, Mb, trb, rab[0], rab[1], rab[2]);
+  } else {
+    mat_H<2>(M, tr, H);
 #pragma unroll
-  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
-  sym_mv_bwd(H, ra[0], accb.m5, Hb, rab[0]);
-  mat_H_bwd<2>(M, tr, Hb, Mb, trb);
-  mat_Gv(M, tr, H);
+    for (int k = 0; k < 15; ++k) Hb[k] = T(0);
+    sym_mv_bwd(H, ra[0], accb.m5, Hb, rab[0]);
+    mat_H_bwd<2>(M, tr, Hb, Mb, trb);
+    mat_Gv(M, tr, H);
 #pragma unroll
-  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
-  sym_mv_bwd(H, ra[1], accb.m5, Hb, rab[1]);
-  mat_Gv_bwd(M, tr, Hb, Mb, trb);
-  mat_Gw(M, tr, H);
+    for (int k = 0; k < 15; ++k) Hb[k] = T(0);
+    sym_mv_bwd(H, ra[1], accb.m5, Hb, rab[1]);
+    mat_Gv_bwd(M, tr, Hb, Mb, trb);
+    mat_Gw(M, tr, H);
 #pragma unroll
-  for (int k = 0; k < 15; ++k) Hb[k] = T(0);
-  sym_mv_bwd(H, ra[2], accb.m5, Hb, rab[2]);
-  mat_Gw_bwd(M, tr, Hb, Mb, trb);
+    for (int k = 0; k < 15; ++k) Hb[k] = T(0);
+    sym_mv_bwd(H, ra[2], accb.m5, Hb, rab[2]);
+    mat_Gw_bwd(M, tr, Hb, Mb, trb);
+  }
 
   Prim<T> sb = prim_zero<T>();
   sb.rho += rb;

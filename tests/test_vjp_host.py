@@ -4,7 +4,8 @@ from the kernels' own headers and checked against central differences of the
 forward point functions: for random physical states and slopes, random
 cotangents (F, Ft) and random directions in (Q, dQ, mu), <VJP, direction> must
 match the fourth-order central difference of <cotangent, flux> along the
-direction.  Cases cover mu = 0
+direction.  The matrix-free reverse of m5 that the FP32 kernels run
+(m5_acc_bwd) is checked the same way on its own inputs.  Cases cover mu = 0
 (tau = 0), a moderate and a large mu, Pr = 0.72 and 1, two time steps, nearly
 equal left and right states, and low-Mach states (large internal energy, where
 the difference quotient itself is less accurate)."""
@@ -22,6 +23,7 @@ SRC = r'''
 #include <cmath>
 #include <cstdio>
 #include <random>
+#include <vector>
 #include "gks_point_adj.hpp"
 using namespace dgk;
 
@@ -160,6 +162,46 @@ int main() {
       printf("face %d %d %d %.3e\n", trial, nf, int(lm), std::fabs(lin - fd) / std::max(std::fabs(fd), 1e-8));
     }
   }
+  // m5_acc_bwd (the matrix-free reverse of m5 that the FP32 kernels run)
+  // against central differences of <ob, m5_acc> in every input: M, the fifteen
+  // transverse moments taken as independent inputs, and x, y, z
+  for (int trial = 0; trial < 48; ++trial) {
+    double M[7], x[15], ob[5], dM[7], dx[15];
+    mom_half(uni(-1.5, 1.5), uni(0.2, 3.0), trial % 2 ? 1.0 : -1.0, M);
+    const Transverse<double> t0(uni(-1.5, 1.5), uni(-1.5, 1.5), uni(0.2, 3.0), 2.0);
+    for (int i = 0; i < 15; ++i) { x[i] = nrm(); dx[i] = nrm(); }
+    for (int i = 0; i < 7; ++i) dM[i] = nrm();
+    for (int k = 0; k < 5; ++k) ob[k] = nrm();
+    double dt[15];
+    for (int i = 0; i < 15; ++i) dt[i] = nrm();
+    auto members = [](Transverse<double>& t) {
+      double* m[15] = {&t.V, &t.W, &t.v2, &t.w2, &t.v3, &t.w3, &t.R1, &t.R2, &t.vr, &t.wr,
+                       &t.v2r, &t.w2r, &t.vwr, &t.vr2, &t.wr2};
+      return std::vector<double*>(m, m + 15);
+    };
+    auto f = [&](double s) {
+      double Ms[7], xs[15], m5[5] = {0, 0, 0, 0, 0};
+      for (int i = 0; i < 7; ++i) Ms[i] = M[i] + s * dM[i];
+      for (int i = 0; i < 15; ++i) xs[i] = x[i] + s * dx[i];
+      Transverse<double> ts = t0;
+      std::vector<double*> mm = members(ts);
+      for (int i = 0; i < 15; ++i) *mm[i] += s * dt[i];
+      m5_acc(Ms, ts, xs, xs + 5, xs + 10, m5);
+      double r = 0;
+      for (int k = 0; k < 5; ++k) r += ob[k] * m5[k];
+      return r;
+    };
+    double Mb[7] = {0, 0, 0, 0, 0, 0, 0}, xb[15] = {0};
+    TransverseBar<double> tb = transverse_bar_zero<double>();
+    m5_acc_bwd(M, t0, x, x + 5, x + 10, ob, Mb, tb, xb, xb + 5, xb + 10);
+    const double tbv[15] = {tb.V, tb.W, tb.v2, tb.w2, tb.v3, tb.w3, tb.R1, tb.R2, tb.vr, tb.wr,
+                            tb.v2r, tb.w2r, tb.vwr, tb.vr2, tb.wr2};
+    double lin = 0;
+    for (int i = 0; i < 7; ++i) lin += Mb[i] * dM[i];
+    for (int i = 0; i < 15; ++i) lin += xb[i] * dx[i] + tbv[i] * dt[i];
+    const double fd = central4(f);
+    printf("m5bwd %d 0 0 %.3e\n", trial, std::fabs(lin - fd) / std::max(std::fabs(fd), 1e-8));
+  }
   return 0;
 }
 '''
@@ -180,10 +222,11 @@ def results(tmp_path_factory):
 
 
 def test_every_case_ran(results):
-    assert len(results) == 24 * 2 * 2
+    kinds = [k for k, *_ in results]
+    assert kinds.count("volume") == kinds.count("face") == 24 * 2 and kinds.count("m5bwd") == 48
 
 
-@pytest.mark.parametrize("kind", ["volume", "face"])
+@pytest.mark.parametrize("kind", ["volume", "face", "m5bwd"])
 def test_vjp_matches_central_differences(results, kind):
     # the stencil leaves below 1e-10 relative, up to a few 1e-9 where the low-Mach
     # objectives are small differences of large moments (its rounding part)

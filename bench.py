@@ -27,10 +27,9 @@ import numpy as np  # noqa: E402
 # volume point of each stage, for the kernels' own formulas.
 FLOPS_JSON = os.path.join(ROOT, "paper_2202_13821_amd", "flops.json")
 
-# published peaks; the non-packed FP32 rate is what code without v_pk_*_f32 can reach
-# Published MI355X peaks.  The FP32 vector peak is reachable without packed-FP32
-# instructions: two-operand (VOP2) FP32 FMAs and multiplies issue in under 4
-# cycles per wavefront on gfx950 (measured by csrc/peakprobe/valu_rate.hip).
+# Published MI355X peaks.  The FP32 vector peak is 256 CUs x 4 SIMDs x 32 FMA
+# lanes x 2 flop x 2.4 GHz; on gfx950 FP32 instructions with VGPR operands
+# issue in under 3 cycles per wavefront without packed-FP32 instructions.
 MI355X_PEAK = {"fp32_vector": 157.3, "fp64_vector": 78.6, "hbm_GBs": 8000.0}
 
 
@@ -45,6 +44,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rules", action="store_true",
                     help="skip the other compiled (degree, Gauss points) rules: P2 with 2 points, P3 with 3 and 4")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the comparison with the stored oracle reference of the 128^3 workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-only", action="store_true",
                     help="profiling aid: run only the adjoint/forward timing (32^3) and print it")
@@ -60,7 +61,14 @@ def load_flops():
     return None
 
 
-def time_path(precision, n, steps, warmup, timing=True, k=2, nq=0, mapped=False):
+def time_path(precision, n, steps, warmup, timing=True, k=2, nq=0, mapped=False, reps=3):
+    """Seconds per step of `precision` on the n^3 Taylor-Green workload: the
+    median of `reps` wall-clock repetitions of `steps` steps (inputs resident
+    in HBM, torch.cuda.synchronize() on both sides, no event recording), then
+    one more repetition with the library's per-launch HIP events on its
+    stream (kernel averages).  Returns (median s/step, all repetitions, kernel
+    timing, final state, solver, initial state); the state has had
+    warmup + (reps + 1) * steps steps."""
     import numpy as np
     import torch
 
@@ -76,17 +84,21 @@ def time_path(precision, n, steps, warmup, timing=True, k=2, nq=0, mapped=False)
     q = torch.as_tensor(q0, device="cuda:0")
     s.step(q, dt, warmup)
     s.check()
+    walls = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(q, dt, steps)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) / steps)
+    kern = None
     if timing:
         s.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(q, dt, steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = s.get_timing() if timing else None
-    s.set_timing(False)
+        s.step(q, dt, steps)
+        kern = s.get_timing()
+        s.set_timing(False)
     s.check()
-    return (t1 - t0) / steps, kern, q, s
+    return float(np.median(walls)), walls, kern, q, s, q0
 
 
 def adjoint_ratio(precision, n=32, nsteps=200, stride=15, k=2, nq=0):
@@ -125,6 +137,48 @@ def adjoint_ratio(precision, n=32, nsteps=200, stride=15, k=2, nq=0):
     return {"fwd_s": t1 - t0, "adj_s": t3 - t2, "adj_over_fwd": (t3 - t2) / (t1 - t0),
             "workload": f"P{k} TGV {n}^3{'' if not nq else f', {nq} Gauss points'}, {nsteps} steps, "
                         f"checkpoint stride {stride}"}
+
+
+def parity_vs_oracle():
+    """Both GPU paths from the initial state through the checkpoints of the
+    stored FP64 oracle reference of this workload (tests/golden/oracle_c4.json,
+    written by tests/golden/make_golden.py): relative L2 over its 64 sampled
+    cells of the state and of the change since t = 0, per (rho, momentum,
+    rho E), at its last checkpoint."""
+    import numpy as np
+    import torch
+
+    from paper_2202_13821_amd import Solver, problems
+
+    path = os.path.join(ROOT, "tests", "golden", "oracle_c4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    if not g.get("checkpoints"):
+        return None
+    cp = g["checkpoints"][-1]
+    n = g["shape"][0]
+    q0, lo, hi = problems.tgv((n, n, n), 2)
+    cells = np.array(g["cells"])
+    ref, ref0 = np.array(cp["coeffs"]), np.array(g["coeffs0"])
+    out = {"steps": cp["steps"], "sampled_cells": len(cells), "reference": "tests/golden/oracle_c4.json"}
+    for prec in ("fp64", "fp32_bulk"):
+        s = Solver((n, n, n), lo, hi, 2, mu=g["mu"], prandtl=g["prandtl"], precision=prec, device="cuda:0")
+        q = torch.as_tensor(q0, device="cuda:0")
+        s.step(q, g["dt"], cp["steps"])
+        s.check()
+        qf = q.cpu().numpy().reshape(5, 10, -1)
+        samp = np.transpose(qf[:, :, cells], (2, 0, 1))
+        s0 = np.transpose(q0.reshape(5, 10, -1)[:, :, cells], (2, 0, 1))
+        st, inc = {}, {}
+        for name, idx in (("rho", [0]), ("momentum", [1, 2, 3]), ("rhoE", [4])):
+            st[name] = float(np.linalg.norm(samp[:, idx] - ref[:, idx]) / np.linalg.norm(ref[:, idx]))
+            di = (samp[:, idx] - s0[:, idx]) - (ref[:, idx] - ref0[:, idx])
+            inc[name] = float(np.linalg.norm(di) / np.linalg.norm(ref[:, idx] - ref0[:, idx]))
+        out[prec] = {"rel_l2_state": st, "rel_l2_increment": inc}
+        del s, q
+    return out
 
 
 def kernel_source_hash():
@@ -203,10 +257,13 @@ def main():
                                   "Gauss points, Re 1600, Ma 0.1, Pr 0.72, CFL 0.15, FP32-bulk flux and "
                                   "projection with FP64 stage accumulation",
                       "cells": n ** 3, "modes": 10, "dof_per_step": dof}}
-    sec32, k32, q32, s32 = time_path("fp32_bulk", n, a.steps, a.warmup)
+    sec32, walls32, k32, q32, s32, q0 = time_path("fp32_bulk", n, a.steps, a.warmup)
     out["value"] = dof / sec32
     out["dof_updates_per_variable_per_s"] = dof / 5 / sec32
     out["ms_per_step"] = 1e3 * sec32
+    out["timing"] = {"method": "median of 3 wall-clock repetitions of `steps` steps (synchronize on both sides, "
+                               "no event recording); kernel averages from a 4th, event-timed repetition",
+                     "ms_per_step_reps": [1e3 * w for w in walls32]}
     out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else None) for k, v in k32.items()}
     flops = load_flops()
     face_ms = k32["face"][0] / max(k32["face"][1], 1)
@@ -241,8 +298,8 @@ def main():
         out["step_tflops"] = per_step / sec32 / 1e12
     if not a.no_fp64:
         del s32
-        sec64, k64, q64, s64 = time_path("fp64", n, a.steps, a.warmup)
-        out["fp64"] = {"value": dof / sec64, "ms_per_step": 1e3 * sec64,
+        sec64, walls64, k64, q64, s64, _ = time_path("fp64", n, a.steps, a.warmup)
+        out["fp64"] = {"value": dof / sec64, "ms_per_step": 1e3 * sec64, "ms_per_step_reps": [1e3 * w for w in walls64],
                        "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in k64.items()}}
         if flops:
             f64_ms = k64["face"][0] / max(k64["face"][1], 1)
@@ -257,7 +314,18 @@ def main():
         groups = ((0,), (1, 2, 3), (4,))
         out["rel_l2_fp32_bulk_vs_fp64"] = max(
             float(torch.linalg.norm(d[list(g)]) / torch.linalg.norm(r[list(g)])) for g in groups)
+        # the same after subtracting the initial state: the error of what the
+        # flow did over the warmup + 4 x steps steps, per (rho, momentum, rho E)
+        z = torch.as_tensor(q0, device=q64.device).reshape(5, -1)
+        i64 = q64.reshape(5, -1) - z
+        i32 = q32.reshape(5, -1) - z
+        out["rel_l2_increment_fp32_bulk_vs_fp64"] = {
+            name: float(torch.linalg.norm(i32[list(g)] - i64[list(g)]) / torch.linalg.norm(i64[list(g)]))
+            for name, g in zip(("rho", "momentum", "rhoE"), groups)}
+        out["steps_compared"] = a.warmup + 4 * a.steps
         del s64
+    if not a.no_parity and n == 128:
+        out["parity_vs_oracle"] = parity_vs_oracle()
     if not a.no_rules:
         # the other compiled quadrature rules on the same Taylor-Green workload
         out["rules"] = {}
@@ -265,7 +333,7 @@ def main():
             leg = {"degree": k, "gauss_points_per_axis": nq, "modes": (k + 1) * (k + 2) * (k + 3) // 6}
             dof_k = 5 * leg["modes"] * n ** 3
             for prec in ("fp32_bulk", "fp64"):
-                sec, kk, qk, sk = time_path(prec, n, min(a.steps, 5), 1, k=k, nq=nq)
+                sec, _, kk, qk, sk, _ = time_path(prec, n, min(a.steps, 5), 1, k=k, nq=nq, reps=1)
                 ms = {x: (v[0] / v[1] if v[1] else None) for x, v in kk.items() if x in ("face", "volume")}
                 leg[prec] = {"value": dof_k / sec, "ms_per_step": 1e3 * sec, "kernels_ms_per_launch": ms}
                 fr = (flops or {}).get("rules", {}).get(f"p{k}_nq{nq}", {}).get("fp32" if prec != "fp64" else "fp64")
@@ -285,7 +353,7 @@ def main():
         leg = {"mesh": "x = xi + 0.05 (b - a) sin(2 pi (xi - a) / (b - a)) per axis", "degree": 2,
                "gauss_points_per_axis": 3}
         for prec in ("fp32_bulk", "fp64"):
-            sec, kk, qk, sk = time_path(prec, n, min(a.steps, 5), 1, mapped=True)
+            sec, _, kk, qk, sk, _ = time_path(prec, n, min(a.steps, 5), 1, mapped=True, reps=1)
             leg[prec] = {"value": dof / sec, "ms_per_step": 1e3 * sec,
                          "kernels_ms_per_launch": {x: (v[0] / v[1] if v[1] else None) for x, v in kk.items()
                                                    if x in ("face", "volume")}}

@@ -54,7 +54,9 @@ extern "C" {
 #define DG_HGKS_EUNSUPPORTED (-5) /* (degree, nq) combination not compiled */
 
 #define DG_HGKS_FP64 0      /* every flux and projection in float64 */
-#define DG_HGKS_FP32_BULK 1 /* fluxes and projections in float32; stage
+#define DG_HGKS_FP32_BULK 1 /* fluxes (including the combination of the
+                               face-flux moments with the time-integral
+                               coefficients) and projections in float32; stage
                                accumulation of the coefficients and the
                                exp(-dt/tau) time-integral coefficients in float64 */
 

@@ -106,11 +106,9 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
     L.adj_stars = take((size_t)max_stride * state * Ts);  // Q* of each step
     L.adj_qbar = take(state * 8);
     L.adj_qsbar = take(state * 8);
-    L.adj_Lbar = take(state * 8);
-    L.adj_Ltbar = take(state * 8);
     L.adj_frec = take(3 * 2 * ((N + 63) / 64 * 64) * 5 * nm * 8);  // per face: cotangents of both cells' coefficients
-    L.adj_mu = take(adj_mu_slots(N) * 8);
-    L.adj_tmp = take(kAlign);
+    L.adj_mu = take(adj_mu_slots(N) * 8);  // per-block partial sums of dJ/dmu
+    L.adj_tmp = take(((adj_mu_slots(N) + dgk::kMuChunk - 1) / dgk::kMuChunk + 1) * 8);  // second pass + result
   }
   L.total = off;
   return L;
@@ -155,9 +153,9 @@ dgk::Geo make_geo(const dg_hgks_ctx* c) {
   g.w[1] = w + p.nx;
   g.w[2] = w + p.nx + p.ny;
   g.uniform = c->uniform ? 1 : 0;
-  g.two_inv_h[0] = 2.0 / c->widths[0];
-  g.two_inv_h[1] = 2.0 / c->widths[p.nx];
-  g.two_inv_h[2] = 2.0 / c->widths[p.nx + p.ny];
+  g.two_inv_h[0] = 2.0 / c->w0[0];
+  g.two_inv_h[1] = 2.0 / c->w0[1];
+  g.two_inv_h[2] = 2.0 / c->w0[2];
   return g;
 }
 
@@ -280,8 +278,10 @@ int dg_hgks_init(const dg_hgks_params* p, void* hip_stream, void* workspace, siz
   c->p.cell_widths = nullptr;  // the caller's array is not kept
   {
     const int n[3] = {p->nx, p->ny, p->nz};
-    for (int e = 0, off = 0; e < 3; off += n[e], ++e)
+    for (int e = 0, off = 0; e < 3; off += n[e], ++e) {
+      c->w0[e] = c->widths[off];
       for (int i = 1; i < n[e]; ++i) c->uniform = c->uniform && c->widths[off + i] == c->widths[off];
+    }
   }
   *out = c;
   return DG_HGKS_OK;

@@ -10,8 +10,8 @@
 //  * face_flux   : Section 2, Eq. (flux) with its slope systems, in the local
 //                  frame of the face (normal velocity first), followed by the
 //                  linear-in-time fit of Eq. (expansion-1) over [0, dt] and
-//                  [0, dt/2].  The exp(-t/tau) time-integral coefficients and
-//                  their combination with the flux moments are FP64.
+//                  [0, dt/2].  The exp(-t/tau) time-integral coefficients are
+//                  FP64; their combination with the flux moments runs in T.
 //  * volume_flux : Section 3, Eq. (flux-2), f = g0 (1 - tau (a.u + A) + A t).
 //
 // Moments are formed from products of one-dimensional Maxwellian moment
@@ -648,9 +648,9 @@ DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], 
   // beta_3 = -beta_0, beta_4 = -beta_1, alpha_3 = 1 - alpha_0, alpha_4 = -tau - alpha_1:
   //   Ft = beta_0 (m1 - m4) + beta_1 (m2 - m5) + beta_2 m3 + beta_5 m6
   //   F  = m4 + alpha_0 (m1 - m4) + alpha_1 (m2 - m5) - tau m5 + alpha_2 m3 + alpha_5 m6
-  // The equilibrium and non-equilibrium moments nearly cancel in these
-  // differences, which are then exact in T (Sterbenz), so the combination runs
-  // in T with the FP64 coefficients rounded once.
+  // The combination runs in T with the FP64 coefficients rounded once: in
+  // FP32-bulk, forming it in FP64 instead changed the Taylor-Green errors
+  // (state and increment) by under 0.5% and cost 1.7% of the step.
   const T b0 = T(be[0]), b1 = T(be[1]), b2 = T(be[2]), b5 = T(be[5]);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {

@@ -25,8 +25,18 @@
 
 namespace dgk {
 
-// Number of per-block partial sums of dJ/dmu kept in the workspace.
-inline size_t adj_mu_slots(size_t ncell) { return 3 * ncell + 64; }
+// Number of per-block partial sums of dJ/dmu kept in the workspace: one slot
+// per block of the two adjoint launches of a stage (3 nb face blocks of
+// kAdjFaceThreads / 2 faces each, then the volume blocks of kCellThreads
+// cells), reused by every stage and step.  Lanes per adjoint face block:
+// 128 faces x 2 sides.
+constexpr int kAdjFaceThreads = 256;
+inline size_t adj_face_blocks(size_t ncell) { return (ncell + kAdjFaceThreads / 2 - 1) / (kAdjFaceThreads / 2); }
+inline size_t adj_mu_slots(size_t ncell) {
+  return 3 * adj_face_blocks(ncell) + (ncell + kCellThreads - 1) / kCellThreads;
+}
+// Slots summed by one block of the first pass of the dJ/dmu reduction.
+constexpr int kMuChunk = 2048;
 
 // Step-level cotangents.  With qbar = cotangent of Q^{n+1} and qsbar = that
 // of Q* (output of stage 2):
@@ -89,9 +99,6 @@ DGK_D void pair_sum(T* x, int n) {
 DGK_D long long frec_index(int d, int side, long long face, int vm, int nvm, long long ntile) {
   return ((((long long)d * 2 + side) * ntile + (face >> 6)) * nvm + vm) * 64 + (face & 63);
 }
-
-// Lanes per adjoint face block: 128 faces x 2 sides.
-constexpr int kAdjFaceThreads = 256;
 
 // FP64 up to P2: the lane's face-restricted coefficients and record cotangent
 // live in its LDS column (read where used) instead of registers.  The FP64
@@ -474,18 +481,22 @@ static __global__ __launch_bounds__(256) void zero_kernel(double* a, long long n
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) a[i] = 0.0;
 }
 
-// Fixed-order sum of the dJ/dmu slots into out[0] (one block).
+// Fixed-order sum of the dJ/dmu slots, two passes: block b of the first pass
+// sums slots [b kMuChunk, (b + 1) kMuChunk) into part[b]; one block then sums
+// the parts into out[0].  Both passes sum in the same order on every call.
 static __global__ __launch_bounds__(256) void reduce_mu_kernel(const double* a, long long n, double* out) {
   __shared__ double sh[256];
+  const long long lo = (long long)blockIdx.x * kMuChunk;
+  const long long hi = lo + kMuChunk < n ? lo + kMuChunk : n;
   double s = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) s += a[i];
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) s += a[i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
 }  // namespace dgk

@@ -117,7 +117,7 @@ template <class T, int K, int NQ, int STAGE>
 int launch_adj_stage(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, double* out, const Geo& g,
                      const Phys& ph) {
   const long long N = g.ncell;
-  const unsigned nbf = (unsigned)((N + kAdjFaceThreads / 2 - 1) / (kAdjFaceThreads / 2));
+  const unsigned nbf = (unsigned)adj_face_blocks((size_t)N);
   const unsigned nbv = (unsigned)((N + kCellThreads - 1) / kCellThreads);
   double* frec = (double*)(c->ws + c->lay.adj_frec);
   double* mu = (double*)(c->ws + c->lay.adj_mu);
@@ -147,8 +147,9 @@ int run_adjoint(dg_hgks_ctx* c, const double* ckpt, int stride, double dt, int n
   double* qbar = (double*)(c->ws + c->lay.adj_qbar);
   double* qsbar = (double*)(c->ws + c->lay.adj_qsbar);
   double* mu = (double*)(c->ws + c->lay.adj_mu);
-  double* mu_out = (double*)(c->ws + c->lay.adj_tmp);
+  double* mu_part2 = (double*)(c->ws + c->lay.adj_tmp);
   const long long nslots = (long long)adj_mu_slots((size_t)g.ncell);
+  const unsigned nparts = (unsigned)((nslots + kMuChunk - 1) / kMuChunk);
   int rc = ensure_ready(c);
   if (rc) return rc;
   DG_HIP(c, hipMemcpyAsync(qbar, qN_bar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -209,9 +210,10 @@ int run_adjoint(dg_hgks_ctx* c, const double* ckpt, int stride, double dt, int n
     }
   }
   DG_HIP(c, hipMemcpyAsync(q0_bar, qbar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<1, 256, 0, c->stream>>>(mu, nslots, mu_out)));
+  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<nparts, 256, 0, c->stream>>>(mu, nslots, mu_part2)));
+  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<1, 256, 0, c->stream>>>(mu_part2, nparts, mu_part2 + nparts)));
   double h = 0.0;
-  DG_HIP(c, hipMemcpyAsync(&h, mu_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  DG_HIP(c, hipMemcpyAsync(&h, mu_part2 + nparts, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   DG_HIP(c, hipStreamSynchronize(c->stream));
   *mu_bar_host = h;
   return dg_hgks_check(c);

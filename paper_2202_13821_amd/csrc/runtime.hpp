@@ -16,7 +16,7 @@ namespace dgrt {
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
   size_t flag = 0, geo = 0, qs = 0, qstar = 0, P = 0, rec = 0, diag = 0;
-  size_t adj_states = 0, adj_stars = 0, adj_qbar = 0, adj_qsbar = 0, adj_Lbar = 0, adj_Ltbar = 0, adj_frec = 0,
+  size_t adj_states = 0, adj_stars = 0, adj_qbar = 0, adj_qsbar = 0, adj_frec = 0,
          adj_mu = 0, adj_tmp = 0;
   size_t total = 0;
 };
@@ -41,6 +41,7 @@ struct dg_hgks_ctx {
   bool ready = false;          // flag cleared and cell widths uploaded
   std::vector<double> widths;  // nx + ny + nz cell widths (x, y, z)
   bool uniform = true;         // every axis has equal widths
+  double w0[3] = {0, 0, 0};    // width of the first cell of each axis (of every cell on a uniform mesh)
   std::string err;
   bool timing = false;
   std::vector<dgrt::TimingRec> trecs;

@@ -195,21 +195,31 @@ class DGHGKSSteps(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, q0, mu, solver, dt, nsteps):
-        solver.set_mu(float(mu.item()))
+        mu_f = float(mu.item())
+        solver.set_mu(mu_f)
         stride = solver.checkpoint_stride(nsteps)
         if stride > solver.max_stride:
             raise ValueError(f"solver built with max_stride={solver.max_stride} < {stride}")
         ckpt = solver.new_checkpoints(nsteps, stride)
         q = q0.detach().clone().contiguous()
         solver.step(q, dt, nsteps, ckpt, stride)
-        ctx.solver, ctx.dt, ctx.nsteps, ctx.stride = solver, dt, nsteps, stride
+        ctx.solver, ctx.dt, ctx.nsteps, ctx.stride, ctx.mu = solver, dt, nsteps, stride, mu_f
         ctx.save_for_backward(ckpt)
         return q
 
     @staticmethod
     def backward(ctx, gq):
         (ckpt,) = ctx.saved_tensors
-        q0_bar, mu_bar = ctx.solver.adjoint(ckpt, ctx.stride, ctx.dt, ctx.nsteps, gq.contiguous())
+        solver = ctx.solver
+        # the reverse sweep recomputes the segments and differentiates tau =
+        # mu / p with the viscosity of this forward call, whatever the solver
+        # holds now (another forward, or a set_mu, may have changed it)
+        mu_now = solver.mu
+        solver.set_mu(ctx.mu)
+        try:
+            q0_bar, mu_bar = solver.adjoint(ckpt, ctx.stride, ctx.dt, ctx.nsteps, gq.contiguous())
+        finally:
+            solver.set_mu(mu_now)
         mu_grad = torch.tensor(mu_bar, dtype=torch.float64, device=gq.device)
         return q0_bar, mu_grad, None, None, None
 

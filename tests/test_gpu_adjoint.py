@@ -119,6 +119,14 @@ def test_adjoint_c5_fp64_vs_central_differences():
 
 
 def test_adjoint_c5_fp32_bulk_vs_fp64():
+    """FP32-bulk adjoint against the FP64 adjoint at C5: the full gradient in
+    relative L2, dJ/dmu, and the directional derivatives <g, v> of the 20 C5
+    directions, each relative to its own FP64 value, |a - b| / |b|.  A
+    direction whose FP64 derivative is below a tenth of the median over the
+    20 is left out: there the relative measure divides by a cancellation
+    (the directions are mostly rho E, to which J is blind).  Tolerance 1e-4
+    (measured: worst 3.5e-5 over the kept directions, 1.7e-4 on the smallest
+    derivative, 30 times below the median)."""
     say("C5 fp32 bulk vs fp64 adjoint")
     s64, q0, dt, n, stride = _c5("fp64")
     _, g64, mu64 = _adjoint(s64, to_dev(q0), dt, n, stride)
@@ -126,17 +134,22 @@ def test_adjoint_c5_fp32_bulk_vs_fp64():
     s32, _, _, _, _ = _c5("fp32_bulk")
     _, g32, mu32 = _adjoint(s32, to_dev(q0), dt, n, stride)
     g64, g32 = to_np(g64), to_np(g32)
-    worst = 0.0
-    for v in _directions(q0, 5):
-        # directional error normalised by |g| |v| (a single directional
-        # derivative can be small by cancellation)
-        a, b = float((g32 * v).sum()), float((g64 * v).sum())
-        worst = max(worst, abs(a - b) / (np.linalg.norm(g64) * np.linalg.norm(v)))
+    pairs = [(float((g32 * v).sum()), float((g64 * v).sum())) for v in _directions(q0)]
+    med = float(np.median([abs(b) for _, b in pairs]))
+    worst, used = 0.0, 0
+    for t, (a, b) in enumerate(pairs):
+        small = abs(b) < 0.1 * med
+        rel = abs(a - b) / abs(b)
+        say(f"  dir {t}: fp32 {a:.9e} fp64 {b:.9e} rel {rel:.2e}{' (left out: small)' if small else ''}")
+        if not small:
+            worst = max(worst, rel)
+            used += 1
     relm = abs(mu32 - mu64) / abs(mu64)
     rel_full = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
-    say(f"  directional rel {worst:.2e}, mu rel {relm:.2e}, full-gradient rel L2 {rel_full:.2e}")
+    say(f"  directional rel (worst of {used}) {worst:.2e}, mu rel {relm:.2e}, full-gradient rel L2 {rel_full:.2e}")
     # float32 fluxes and VJPs at Mach 0.1 with FP64 accumulation
-    assert worst <= 1e-4 and relm <= 1e-3 and rel_full <= 1e-3
+    assert used >= 15
+    assert worst <= 1e-4 and relm <= 1e-6 and rel_full <= 1e-4
 
 
 def test_adjoint_checkpoint_segments_bitwise():
@@ -165,3 +178,29 @@ def test_autograd_function_matches_direct_call():
     _, g, mub = _adjoint(s, to_dev(q0), 2e-3, 5, s.checkpoint_stride(5))
     assert torch.equal(q0t.grad, g)
     assert mu.grad.item() == mub
+
+
+def test_autograd_backward_uses_the_forward_mu():
+    """Two forwards with different mu on one solver, then the backward of the
+    first: its gradient is that of the first trajectory (the backward runs
+    the adjoint at the first forward's mu), and the solver's mu is left as
+    the last forward set it."""
+    say("autograd mu")
+    rng = np.random.default_rng(901)
+    shape = (5, 4, 4)
+    q0 = IN.random_field(rng, shape, 10, amp=0.03)
+    s, _ = pair(shape, 2, (0, 0, 0), (1, 1, 1), mu=0.01, pr=0.72, max_stride=3)
+    q0t = to_dev(q0).requires_grad_(True)
+    mu1 = torch.tensor(0.01, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    mu2 = torch.tensor(0.03, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    qN1 = steps(q0t, mu1, s, 2e-3, 5)
+    qN2 = steps(q0t, mu2, s, 2e-3, 5)
+    assert s.mu == 0.03
+    kinetic_energy(qN1, s).backward()
+    assert s.mu == 0.03
+    s.set_mu(0.01)
+    _, g, mub = _adjoint(s, to_dev(q0), 2e-3, 5, s.checkpoint_stride(5))
+    assert torch.equal(q0t.grad, g)
+    assert mu1.grad.item() == mub
+    assert mu2.grad is None
+    del qN2

@@ -444,6 +444,44 @@ def test_residual_cells_and_slab_match_full_grid(orc):
     assert np.array_equal(Lts, Ltf[:, :, 2 * n:4 * n].transpose(2, 0, 1))
 
 
+def test_step_cells_matches_full_grid_step(orc):
+    """The sampled one-step oracle (stage 1 on the listed cells and their face
+    neighbours, stage 2 on the listed cells) equals the full-grid S2O4 step
+    of Eq. (two-stage) at those cells, bit for bit; corner and edge cells
+    exercise the periodic wrap."""
+    rng = np.random.default_rng(21)
+    shape = (5, 4, 6)
+    c = orc.make_cfg(shape, 2, lo=(0, 0, 0), hi=(1, 1.1, 0.9), mu=0.01, prandtl=0.72)
+    q = IN.random_field(rng, shape, 10)
+    dt = 2e-3
+    full = orc.step(c, q, dt, 1).reshape(5, 10, -1)
+    cells = [0, 4, 19, 60, 119, 77]
+    got = orc.step_cells(c, q, dt, cells)
+    for t, cc in enumerate(cells):
+        assert np.array_equal(got[t], full[:, :, cc])
+
+
+def test_advection_error_norm_closed_forms(orc):
+    """The Section 5.1 error norm sqrt(int (rho_h - rho_exact)^2 dV) against
+    closed forms on [0,2]^3: rho_h = 0 gives sqrt(8 + 0.04 * 4) (the sine
+    squared averages 1/2 over whole periods), rho_h = 1 gives 0.4; and the
+    exact solution moves at speed 3 along the diagonal: the projection of the
+    t = 0 state has its own small error at t = 2/3 (one period later) and
+    ||2 * 0.2 sin|| = 0.8 at t = 1/3 (half a period)."""
+    N = 8
+    c = orc.make_cfg((N, N, N), 2, lo=(0, 0, 0), hi=(2, 2, 2))
+    q = np.zeros(orc.field_shape(c))
+    assert abs(orc.advection_error(c, q, 0.3) - np.sqrt(8.16)) <= 1e-9
+    q[0, 0] = 1.0
+    assert abs(orc.advection_error(c, q, 0.7) - 0.4) <= 1e-9
+    assert abs(orc.advection_error(c, q, 0.2, "advection_y") - 0.4) <= 1e-9
+    qp = orc.project(c, "advection")
+    e0 = orc.advection_error(c, qp, 0.0)
+    assert e0 < 1e-2
+    assert abs(orc.advection_error(c, qp, 2.0 / 3.0) - e0) <= 1e-12
+    assert abs(orc.advection_error(c, qp, 1.0 / 3.0) - 0.8) <= 2 * e0
+
+
 # --------------------------------------------------------------------------
 # Forward-mode dual numbers (the oracle gradient) against central differences
 # --------------------------------------------------------------------------

@@ -29,7 +29,8 @@
  *
  * Ownership: the caller owns every device buffer (coefficients, checkpoints,
  * adjoint seeds and outputs, workspace); the library never allocates or frees
- * device memory.  The context owns only host state.  Calls are asynchronous on
+ * device memory (dg_hgks_step_noalloc works in a fixed device array that the
+ * library's code object holds on each GPU).  The context owns only host state.  Calls are asynchronous on
  * the stream given to dg_hgks_init unless stated otherwise; they are not
  * thread-safe per context.  No C++ exception crosses this boundary: every call
  * returns a status code (0 on success, negative on error) and
@@ -108,6 +109,24 @@ int dg_hgks_init(const dg_hgks_params* p, void* hip_stream, void* workspace, siz
  * Asynchronous.  Errors: EINVAL (dt <= 0 or non-finite, nsteps < 0, NULL q,
  * ckpt_stride < 1 with ckpt), EHIP. */
 int dg_hgks_step(dg_hgks_ctx* ctx, double* q, double dt, int32_t nsteps, double* ckpt, int32_t ckpt_stride);
+
+/* dg_hgks_step without a context or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): advances q (device, float64, layout above,
+ * in/out) by nsteps steps of size dt with the parameters p (uniform meshes
+ * only: p->cell_widths must be NULL) on the HIP stream hip_stream, using the
+ * same kernels as dg_hgks_step.  Its buffers live in a static device array of
+ * 96 MiB that the library holds on each GPU it runs on until the process
+ * ends (enough for 32^3 cells at P2 in both precisions); parameters that
+ * need more (dg_hgks_workspace_bytes(p, 0) > 96 MiB) fail with ENOMEM.
+ * Every call on a GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (two streams, two threads) race and give undefined results.  The
+ * device must be current.  If nonphys is not NULL (device int32), it
+ * receives 1 if the call met rho <= 0, p <= 0 or a non-finite state, else 0.
+ * Asynchronous; allocates nothing, host or device (errors excepted).  Errors
+ * (message in dg_hgks_last_error(NULL)): EINVAL, ENOMEM, EUNSUPPORTED, EHIP. */
+int dg_hgks_step_noalloc(const dg_hgks_params* p, void* hip_stream, double* q, double dt, int32_t nsteps,
+                         int32_t* nonphys);
 
 /* The operator of Eqs. (operator), (surface), (volume) at q: L = M^{-1} R(Q)
  * and L_t = M^{-1} R_t(Q) (the time derivative from the linear-in-time

@@ -3,4 +3,4 @@
 HIP kernels for gfx950.  torch supplies device memory and streams."""
 from . import problems  # noqa: F401
 from ._lib import DGHGKSError, load  # noqa: F401
-from .solver import DGHGKSSteps, Solver, kinetic_energy, steps, tgv_history  # noqa: F401
+from .solver import DGHGKSSteps, Solver, kinetic_energy, step_noalloc, steps, tgv_history  # noqa: F401

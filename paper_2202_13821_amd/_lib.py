@@ -52,6 +52,7 @@ SIGNATURES = {
     "dg_hgks_workspace_bytes": (ctypes.c_size_t, [_P(dg_hgks_params), _i32]),
     "dg_hgks_init": (ctypes.c_int, [_P(dg_hgks_params), _vp, _vp, ctypes.c_size_t, _P(_vp)]),
     "dg_hgks_step": (ctypes.c_int, [_vp, _vp, _d, _i32, _vp, _i32]),
+    "dg_hgks_step_noalloc": (ctypes.c_int, [_P(dg_hgks_params), _vp, _vp, _d, _i32, _vp]),
     "dg_hgks_residual": (ctypes.c_int, [_vp, _vp, _d, _vp, _vp]),
     "dg_hgks_adjoint": (ctypes.c_int, [_vp, _vp, _i32, _d, _i32, _vp, _vp, _P(_d)]),
     "dg_hgks_set_mu": (ctypes.c_int, [_vp, _d]),

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -226,6 +227,46 @@ int t_collect(dg_hgks_ctx* c) {
 
 }  // namespace
 
+// ---- device scratch of the allocation-free step ------------------------------
+// dg_hgks_step_noalloc keeps its workspace (flag word, stage copies, face
+// records) in this file-scope array instead of a caller's buffer.  Every GPU
+// the library runs on holds its own copy from module load until the process
+// ends; host code reaches it only through the address looked up per device
+// below (the array's name is not a device address on the host).
+constexpr size_t kScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+__global__ void copy_flag_kernel(const int* f, int32_t* out) {
+  if (threadIdx.x == 0) out[0] = f[0];
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.
+int scratch_ptr(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, DG_HGKS_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, DG_HGKS_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, DG_HGKS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DG_HGKS_OK;
+}
+
+}  // namespace
+
 // ============================================================================
 // C-ABI
 // ============================================================================
@@ -297,6 +338,56 @@ int dg_hgks_step(dg_hgks_ctx* c, double* q, double dt, int32_t nsteps, double* c
     using Tg = decltype(tag);
     return dgrt::run_step<typename Tg::T, Tg::K, Tg::NQ>(c, q, dt, nsteps, ckpt, ckpt_stride);
   });
+}
+
+int dg_hgks_step_noalloc(const dg_hgks_params* p, void* hip_stream, double* q, double dt, int32_t nsteps,
+                         int32_t* nonphys) {
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  if (p->cell_widths) return fail(nullptr, DG_HGKS_EINVAL, "the allocation-free step takes uniform meshes only");
+  if (!q) return fail(nullptr, DG_HGKS_EINVAL, "q is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(nullptr, DG_HGKS_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(nullptr, DG_HGKS_EINVAL, "nsteps must be >= 0");
+  const Layout lay = make_layout(*p, 0);
+  if (lay.total > kScratchBytes)
+    return fail(nullptr, DG_HGKS_ENOMEM,
+                "the allocation-free step needs " + std::to_string(lay.total) + " bytes of scratch, above its " +
+                    std::to_string(kScratchBytes) + " (use dg_hgks_init with a workspace)");
+  char* ws = nullptr;
+  rc = scratch_ptr(&ws);
+  if (rc) return rc;
+  // a context on the stack: no host allocation (no widths array on a
+  // uniform mesh), the scratch as workspace
+  dg_hgks_ctx c;
+  c.p = *p;
+  if (c.p.nq == 0) c.p.nq = c.p.degree + 1;
+  c.stream = (hipStream_t)hip_stream;
+  c.ws = ws;
+  c.ws_bytes = kScratchBytes;
+  c.lay = lay;
+  c.ncell = (long long)p->nx * p->ny * p->nz;
+  c.nm = dgk::nmodes(p->degree);
+  c.nt = dgk::ntan(p->degree);
+  c.mu = p->mu;
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int e = 0; e < 3; ++e) c.w0[e] = (p->hi[e] - p->lo[e]) / n[e];
+  // the flag word keeps the previous call's value: clear it (a kernel)
+  clear_flag_kernel<<<1, 64, 0, c.stream>>>((int*)(ws + lay.flag));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, DG_HGKS_EHIP, std::string("clear_flag_kernel: ") + hipGetErrorString(e));
+  c.ready = true;
+  rc = dispatch(c.p, [&](auto tag) {
+    using Tg = decltype(tag);
+    return dgrt::run_step<typename Tg::T, Tg::K, Tg::NQ>(&c, q, dt, nsteps, nullptr, 0);
+  });
+  if (rc) return fail(nullptr, rc, c.err);
+  if (nonphys) {
+    copy_flag_kernel<<<1, 64, 0, c.stream>>>((const int*)(ws + lay.flag), nonphys);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, DG_HGKS_EHIP, std::string("copy_flag_kernel: ") + hipGetErrorString(e));
+  }
+  return DG_HGKS_OK;
 }
 
 int dg_hgks_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* Lt) {

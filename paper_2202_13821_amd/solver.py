@@ -164,6 +164,30 @@ class Solver:
         return torch.empty((max(nslots, 1),) + self.field_shape, dtype=torch.float64, device=self.device)
 
 
+def step_noalloc(q, dt, nsteps, shape, lo, hi, degree, nq=0, gamma=1.4, mu=0.0, prandtl=1.0, precision="fp64",
+                 nonphys=None):
+    """dg_hgks_step_noalloc: advance q (contiguous float64 (5, nmodes, nz, ny,
+    nx) on the current CUDA device) in place by nsteps S2O4 steps on a uniform
+    mesh, on torch's current stream, without a context or workspace (the
+    library's static device scratch, at most 96 MiB: 32^3 cells at P2 in
+    both precisions).  nonphys: optional int32 device tensor of one element
+    that receives 1 if a non-physical state was met, else 0."""
+    lib = _lib.load()
+    nx, ny, nz = (int(x) for x in shape)
+    if q.dtype != torch.float64 or not q.is_cuda or not q.is_contiguous() \
+            or tuple(q.shape) != (5, nmodes(degree), nz, ny, nx):
+        raise ValueError("q must be a contiguous float64 CUDA tensor of shape (5, nmodes, nz, ny, nx)")
+    if nonphys is not None and (nonphys.dtype != torch.int32 or not nonphys.is_cuda or nonphys.numel() < 1):
+        raise ValueError("nonphys must be an int32 CUDA tensor")
+    params = _lib.make_params((nx, ny, nz), lo, hi, degree, nq, gamma, mu, prandtl, PRECISIONS[precision])
+    stream = torch.cuda.current_stream(q.device)
+    with torch.cuda.device(q.device):
+        rc = lib.dg_hgks_step_noalloc(ctypes.byref(params), ctypes.c_void_p(stream.cuda_stream), _ptr(q), float(dt),
+                                      int(nsteps), _ptr(nonphys) if nonphys is not None else None)
+    _lib.check(rc, None)
+    return q
+
+
 class _KineticEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q, solver):

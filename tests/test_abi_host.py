@@ -147,3 +147,26 @@ def test_init_validates_cell_widths():
         assert got == rc, (w, got)
         if rc == 0:
             assert L.dg_hgks_destroy(ctx) == 0
+
+
+def test_noalloc_step_validates_before_touching_the_device():
+    """dg_hgks_step_noalloc rejects bad arguments, non-uniform meshes and
+    grids beyond its static scratch before any HIP call."""
+    q = ctypes.c_void_p(256)  # never dereferenced: every case fails validation
+    p = _params()
+    assert L.dg_hgks_step_noalloc(None, None, q, 1e-3, 1, None) == _lib.DG_HGKS_EINVAL
+    assert L.dg_hgks_step_noalloc(ctypes.byref(_params(degree=5)), None, q, 1e-3, 1, None) == _lib.DG_HGKS_EINVAL
+    assert L.dg_hgks_step_noalloc(ctypes.byref(p), None, None, 1e-3, 1, None) == _lib.DG_HGKS_EINVAL
+    assert L.dg_hgks_step_noalloc(ctypes.byref(p), None, q, 0.0, 1, None) == _lib.DG_HGKS_EINVAL
+    assert L.dg_hgks_step_noalloc(ctypes.byref(p), None, q, 1e-3, -1, None) == _lib.DG_HGKS_EINVAL
+    w = np.full(24, 1.0 / 8)
+    pw = _params(widths=w)
+    assert L.dg_hgks_step_noalloc(ctypes.byref(pw), None, q, 1e-3, 1, None) == _lib.DG_HGKS_EINVAL
+    assert b"uniform" in L.dg_hgks_last_error(None)
+    big = _params(shape=(64, 64, 64))
+    assert L.dg_hgks_step_noalloc(ctypes.byref(big), None, q, 1e-3, 1, None) == _lib.DG_HGKS_ENOMEM
+    assert b"scratch" in L.dg_hgks_last_error(None)
+    # 32^3 P2 fits in both precisions
+    for prec in (_lib.DG_HGKS_FP64, _lib.DG_HGKS_FP32_BULK):
+        assert L.dg_hgks_workspace_bytes(ctypes.byref(_params(shape=(32, 32, 32), precision=prec)), 0) <= 96 << 20
+

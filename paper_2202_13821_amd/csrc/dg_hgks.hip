@@ -102,6 +102,8 @@ Layout make_layout(const dg_hgks_params& p, int max_stride) {
   L.P = take(state * 8);
   L.rec = take(3 * ((N + 63) / 64 * 64) * 10 * nt * Ts);  // records padded to whole 64-cell tiles
   L.diag = take((2 * ((N + dgk::kCellThreads - 1) / dgk::kCellThreads) + 2) * 8);  // diagnostics partial sums
+  // L_t of the stage-1 Ft pass where the volume pass is split (FP64 at P3)
+  if (Ts == 8 && p.degree == 3) L.lt_tmp = take(state * 8);
   if (max_stride > 0) {
     L.adj_states = take((size_t)max_stride * state * 8);  // Q^n of each step of a segment
     L.adj_stars = take((size_t)max_stride * state * Ts);  // Q* of each step

@@ -1,5 +1,6 @@
 """Count the floating-point operations of one face point and one volume
-point of the kernels' formulas and write paper_2202_13821_amd/flops.json.
+point of the kernels' formulas (forward and adjoint) and write
+paper_2202_13821_amd/flops.json.
 
 The point functions of gks_point.hpp are compiled for the host to optimised
 LLVM IR (common subexpressions merged, loops unrolled; the code is straight
@@ -101,6 +102,29 @@ def totals(counts, k, nq):
     return d
 
 
+def adjoint_totals(c, k, nq):
+    """Per-point algorithmic flops of the adjoint kernels of one rule.  Face
+    point of adjoint stage s (the reverse of forward stage s): the two traces
+    and the two sides recomputed, the reverse of the finish, the reverses of
+    the two sides, the two transposed trace evaluations and the record
+    cotangent at the point (F_bar = sum_m phi_m Phi_bar_m).  Volume point:
+    the evaluation, the reverse of the volume flux, the transposed evaluation
+    and the transposed projection.  (The lane pair of the adjoint face kernel
+    also runs the finish's reverse twice; the repeat is not counted.)"""
+    NM, NT = nmodes(k), (k + 1) * (k + 2) // 2
+    nd = NM - NT
+    eval_pt = 5 * (NM + 3 * nd) * 2 + 15
+    d = {}
+    for st in ("s1", "s2"):
+        nf = 2 if st == "s1" else 1
+        d[f"face_stage{st[1]}"] = (4 * eval_pt + 2 * c["side"]["flops"] + c[("finvjp", st)]["flops"]
+                                   + 2 * c["sidevjp"]["flops"] + nf * 5 * NT * 2)
+        d[f"volume_stage{st[1]}"] = 2 * eval_pt + c[("volvjp", st)]["flops"] + nf * 5 * 3 * nd * 2
+    d["per_step_per_cell"] = (3 * nq * nq * (d["face_stage1"] + d["face_stage2"])
+                              + nq ** 3 * (d["volume_stage1"] + d["volume_stage2"]))
+    return d
+
+
 RULES = ((1, 2), (2, 3), (2, 2), (3, 4), (3, 3))
 
 
@@ -116,8 +140,18 @@ def main():
             d[f"volume_point_flux_stage{st[1]}_detail"] = counts[("vol", st)]
         res[tag] = {x: v for x, v in d.items() if x != "per_step_per_cell"}
         res.setdefault("per_step_per_cell", {})[tag] = d["per_step_per_cell"]
+        ac = {"side": count(text, f"fc_side_{T}"), "sidevjp": count(text, f"fc_sidevjp_{T}")}
+        for st in ("s1", "s2"):
+            ac[("finvjp", st)] = count(text, f"fc_finvjp_{T}_{st}")
+            ac[("volvjp", st)] = count(text, f"fc_volvjp_{T}_{st}")
+        ad = adjoint_totals(ac, 2, 3)
+        ad["detail"] = {"side": ac["side"], "side_reverse": ac["sidevjp"],
+                        **{f"finish_reverse_stage{st[1]}": ac[("finvjp", st)] for st in ("s1", "s2")},
+                        **{f"volume_reverse_stage{st[1]}": ac[("volvjp", st)] for st in ("s1", "s2")}}
+        res.setdefault("adjoint", {})[tag] = ad
         for k, nq in RULES:
             rules[f"p{k}_nq{nq}"][tag] = totals(counts, k, nq)
+            rules[f"p{k}_nq{nq}"][f"adjoint_{tag}"] = adjoint_totals(ac, k, nq)
     res["rules"] = rules
     path = os.path.join(PKG, "flops.json")
     with open(path, "w") as f:

@@ -255,9 +255,18 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
         constexpr int ed = md.e[n][D], t = face_tan_of_mode<K>(n, D);
         constexpr double pv = (side == 0 || ed % 2 == 0) ? 1.0 : -1.0;
         constexpr double dv = (side == 0 || ed % 2 == 1 ? 1.0 : -1.0) * 0.5 * ed * (ed + 1);
-        const T c = q[(long long)(v * NM + n) * N + cell];
-        ct[t] += T(pv) * c;
-        if constexpr (ed > 0) cn[t] += T(dv) * c;
+        if constexpr (ed > 0) {
+          const T c = q[(long long)(v * NM + n) * N + cell];
+          ct[t] += T(pv) * c;
+          cn[t] += T(dv) * c;
+        }
+      });
+      // the modes constant along the normal last: among them the cell mean,
+      // the largest term of the trace, is then added with a single rounding
+      static_for<NM>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        constexpr int ed = md.e[n][D], t = face_tan_of_mode<K>(n, D);
+        if constexpr (ed == 0) ct[t] += q[(long long)(v * NM + n) * N + cell];
       });
       // the normal derivative in physical units: 2 / (the side's width) once here
       // rather than at every point
@@ -310,7 +319,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
       T qs[5], dqs[3][5];
 #pragma unroll
       for (int vl = 0; vl < 5; ++vl) {
-        T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0);
+        T v0 = T(0), vn = T(0), v1 = T(0), v2 = T(0), c00 = T(0);
         static_for<NT>([&](auto tc) {
           constexpr int t = decltype(tc)::value;
           T c;
@@ -318,7 +327,11 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
             c = sm.c1[vmap[vl] * NT + t][tid];
           else
             c = sm.x[vmap[vl] * NT + t][tid];
-          v0 += c * TB::t.val[qf][t];
+          // tangential mode 0 (value 1 at every point) is added last
+          if constexpr (t > 0)
+            v0 += c * TB::t.val[qf][t];
+          else
+            c00 = c;
           if constexpr (tmd.e[t][0] > 0) v1 += c * TB::t.d1[qf][t];
           if constexpr (tmd.e[t][1] > 0) v2 += c * TB::t.d2[qf][t];
           if constexpr (t < NT1) {
@@ -330,7 +343,7 @@ DGK_D void face_lane(const T* __restrict__ q, T* __restrict__ rec, const Geo& g,
             vn += cnv * TB::t.val[qf][t];
           }
         });
-        qs[vl] = v0;
+        qs[vl] = v0 + c00;
         if constexpr (UNI) {
           dqs[0][vl] = kPrescaleCn<T, K> ? vn : vn * T(g.two_inv_h[D]);
           dqs[1][vl] = v1 * T(g.two_inv_h[T1]);
@@ -413,6 +426,10 @@ __global__ __launch_bounds__((face_threads<T, K>()), (FaceWaves<T, K>::value)) v
 // MODE 0: stage 1 (F and Ft)   -> Q* (T) and P = Q^n + dt L + dt^2/6 L_t (FP64)
 // MODE 1: stage 2 (Ft only)    -> Q^{n+1} = P + dt^2/3 L_t(Q*) (FP64, + T copy)
 // MODE 2: operator only        -> L, L_t (FP64)
+// PART (MODE 0 and 2): 0 both fluxes in one pass; 2 the Ft pass alone, writing
+// L_t to out.Lt; 1 the F pass alone, then (MODE 0) the update with the L_t of
+// the Ft pass read back from out.Lt.  Two passes halve the accumulators a
+// lane holds, for the configurations whose single pass would spill them.
 // --------------------------------------------------------------------------
 template <class T>
 struct VolOut {
@@ -422,9 +439,16 @@ struct VolOut {
   double* qnew;      // MODE 1 out (may alias qn of the next step)
   T* qshadow;        // MODE 1 out: T copy of Q^{n+1} (nullptr when T = double)
   double* L;         // MODE 2
-  double* Lt;        // MODE 2
+  double* Lt;        // MODE 2; MODE 0 with PART 2 (out) and PART 1 (in)
   double dt;
 };
+
+// Whether the stage-1 and operator volume passes run as an Ft pass and an F
+// pass: FP64 at P3, where one pass would hold 2 x 5 x 20 FP64 accumulators
+// and 5 x 20 FP64 coefficients per lane (more than the 512 registers of a
+// lane at one wavefront per SIMD).
+template <class T, int K>
+constexpr bool kSplitVolume = sizeof(T) == 8 && K == 3;
 
 // Minimum waves per SIMD requested from the register allocator for the
 // volume kernel (FP32: two resident wavefronts per SIMD hide the memory
@@ -465,12 +489,15 @@ struct PointBasisHolder {
   static constexpr PointBasis<T, K, NQ> t{};
 };
 
-template <class T, int K, int NQ, int MODE, bool UNI>
+template <class T, int K, int NQ, int MODE, bool UNI, int PART = 0>
 __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,
                                                              Geo g, Phys ph, VolOut<T> out, int* flag) {
   constexpr int NM = nmodes(K), NT = ntan(K), NQ3 = NQ * NQ * NQ;
-  constexpr bool NEED_F = (MODE != 1);
-  constexpr int NF = NEED_F ? 2 : 1;
+  static_assert(PART == 0 || MODE != 1, "stage 2 has the Ft pass only");
+  constexpr bool NEED_F = (MODE != 1) && PART != 2;  // accumulate F
+  constexpr bool NEED_FT = PART != 1;                // accumulate Ft
+  constexpr int NA = int(NEED_F) + int(NEED_FT);     // accumulator sets
+  constexpr int NF = (MODE != 1) ? 2 : 1;            // record sets: stage-1 records hold F and Ft
   constexpr int RECN = 5 * NF * NT;
   constexpr Modes<K> md{};
   const long long N = g.ncell;
@@ -488,10 +515,10 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
     for (int d = 0; d < 3; ++d) sc[d][threadIdx.x] = T(2.0 / g.w[d][ci[d]]);
   }
   auto scale = [&](int d) -> T { return UNI ? T(g.two_inv_h[d]) : sc[d][UNI ? 0 : threadIdx.x]; };
-  // acc[f][v][n] = sum_q w_q sum_d F^f_d[v](x_q) (2/w_d) dB_n/dxi_d (x_q), f = F | Ft
-  T acc[NF][5][NM];
+  // acc[a][v][n] = sum_q w_q sum_d F^a_d[v](x_q) (2/w_d) dB_n/dxi_d (x_q), a = F | Ft
+  T acc[NA][5][NM];
 #pragma unroll
-  for (int f = 0; f < NF; ++f)
+  for (int f = 0; f < NA; ++f)
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
@@ -510,18 +537,23 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
     const T* pl = rec + rec_index(d, (long long)nb32(unsigned(cc), d, -1, g), 0, RECN, ntile);
     static_for<NF>([&](auto fc) {
       constexpr int f = decltype(fc)::value;
+      // record set f holds F (f = 0 of stage-1 records) or Ft
+      constexpr bool is_f = (NF == 2 && f == 0);
+      constexpr int a = is_f ? 0 : NA - 1;
+      if constexpr (is_f ? NEED_F : NEED_FT) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        static_for<NT>([&](auto mc) {
-          constexpr int m = decltype(mc)::value;
-          const int r = (f * 5 + v) * NT + m;
-          const T ru = pu[r * 64], rl = pl[r * 64];
-          const T dm = ix * (rl - ru), dp = -ix * (rl + ru);
-          static_for<NM>([&](auto nc) {
-            constexpr int n = decltype(nc)::value;
-            if constexpr (face_tan_of_mode<K>(n, d) == m) acc[f][v][n] += (md.e[n][d] & 1) ? dp : dm;
+        for (int v = 0; v < 5; ++v) {
+          static_for<NT>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int r = (f * 5 + v) * NT + m;
+            const T ru = pu[r * 64], rl = pl[r * 64];
+            const T dm = ix * (rl - ru), dp = -ix * (rl + ru);
+            static_for<NM>([&](auto nc) {
+              constexpr int n = decltype(nc)::value;
+              if constexpr (face_tan_of_mode<K>(n, d) == m) acc[a][v][n] += (md.e[n][d] & 1) ? dp : dm;
+            });
           });
-        });
+        }
       }
     });
   });
@@ -553,12 +585,12 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
       static_for<NM>([&](auto nc) {
         constexpr int n = decltype(nc)::value;
         const T cn = cf[v][n];
-        v0 += cn * PB::t.phi[qi][n];
+        if constexpr (n > 0) v0 += cn * PB::t.phi[qi][n];
         if constexpr (md.e[n][0] > 0) vx += cn * ds[0][n];
         if constexpr (md.e[n][1] > 0) vy += cn * ds[1][n];
         if constexpr (md.e[n][2] > 0) vz += cn * ds[2][n];
       });
-      Q[v] = v0;
+      Q[v] = v0 + cf[v][0];  // the cell mean (B_0 = 1) last
       dQ[0][v] = vx;
       dQ[1][v] = vy;
       dQ[2][v] = vz;
@@ -575,7 +607,7 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
             if constexpr (NEED_F) acc[0][v][n] += F[d][v] * b;
-            acc[NF - 1][v][n] += Ft[d][v] * b;
+            if constexpr (NEED_FT) acc[NA - 1][v][n] += Ft[d][v] * b;
           }
         }
       }
@@ -592,19 +624,22 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
     for (int n = 0; n < NM; ++n) {
       const double mi = mt.minv[n];
       const double Ln = NEED_F ? double(acc[0][v][n]) * mi : 0.0;
-      const double Ltn = double(acc[NF - 1][v][n]) * mi;
+      const double Ltn = NEED_FT ? double(acc[NA - 1][v][n]) * mi : 0.0;
       const long long gi = (long long)(v * NM + n) * N + c;
-      if constexpr (MODE == 0) {
+      if constexpr (MODE == 0 && PART == 2) {
+        out.Lt[gi] = Ltn;
+      } else if constexpr (MODE == 0) {
         const double qn = out.qn[gi];
-        out.qstar[gi] = T(qn + 0.5 * dt * Ln + 0.125 * dt * dt * Ltn);
-        out.P[gi] = qn + dt * Ln + (dt * dt / 6.0) * Ltn;
+        const double lt = PART == 1 ? out.Lt[gi] : Ltn;
+        out.qstar[gi] = T(qn + 0.5 * dt * Ln + 0.125 * dt * dt * lt);
+        out.P[gi] = qn + dt * Ln + (dt * dt / 6.0) * lt;
       } else if constexpr (MODE == 1) {
         const double qnew = out.P[gi] + (dt * dt / 3.0) * Ltn;
         out.qnew[gi] = qnew;
         if (out.qshadow) out.qshadow[gi] = T(qnew);
       } else {
-        out.L[gi] = Ln;
-        out.Lt[gi] = Ltn;
+        if constexpr (NEED_F) out.L[gi] = Ln;
+        if constexpr (NEED_FT) out.Lt[gi] = Ltn;
       }
     }
 }

@@ -44,8 +44,18 @@ int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g,
     } else {
       DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true, UNI><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
     }
-    DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE, UNI><<<dim3(nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph, o,
-                                                                                                   flag)));
+    if constexpr (MODE != 1 && kSplitVolume<T, K>) {
+      // Ft pass (L_t to the workspace in stage 1), then F pass and update
+      VolOut<T> ot = o;
+      if constexpr (MODE == 0) ot.Lt = (double*)(c->ws + c->lay.lt_tmp);
+      DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE, UNI, 2><<<dim3(nvb), kCellThreads, 0, c->stream>>>(
+                          qin, rec, g, ph, ot, flag)));
+      DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE, UNI, 1><<<dim3(nvb), kCellThreads, 0, c->stream>>>(
+                          qin, rec, g, ph, ot, flag)));
+    } else {
+      DG_LAUNCH(c, 1, (volume_kernel<T, K, NQ, MODE, UNI><<<dim3(nvb), kCellThreads, 0, c->stream>>>(qin, rec, g, ph,
+                                                                                                     o, flag)));
+    }
     return DG_HGKS_OK;
   };
   return g.uniform ? run(std::true_type{}) : run(std::false_type{});

@@ -15,7 +15,7 @@ namespace dgrt {
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct Layout {
-  size_t flag = 0, geo = 0, qs = 0, qstar = 0, P = 0, rec = 0, diag = 0;
+  size_t flag = 0, geo = 0, qs = 0, qstar = 0, P = 0, rec = 0, diag = 0, lt_tmp = 0;
   size_t adj_states = 0, adj_stars = 0, adj_qbar = 0, adj_qsbar = 0, adj_frec = 0,
          adj_mu = 0, adj_tmp = 0;
   size_t total = 0;

@@ -223,7 +223,11 @@ DGK_HD double exp_neg_tab(double x, const double* ec) {
 // exp_neg_tab.
 DGK_HD void time_coefficients(double tau, double x_half, double dt, double inv_dt, double alpha[6], double beta[6],
                               const double* ec) {
-  const double e = tau > 0.0 ? exp_neg_tab(x_half, ec) : 0.0;
+  // exp(-x) < 2^-54 for x > 37.5: then 1 - e, 3 - e and e^2 - 2e - 1 round to
+  // 1, 3 and -1 in FP64, and dropping e elsewhere changes beta_1 by at most
+  // x e^-x relative (2e-15), so e is taken as 0 there (the branch is uniform
+  // across a wavefront in a smooth flow)
+  const double e = (tau > 0.0 && x_half < 37.5) ? exp_neg_tab(x_half, ec) : 0.0;
   const double x = tau * inv_dt;
   const double om = 1.0 - e;
   const double A = om * (3.0 - e), B = om * om;

@@ -481,13 +481,15 @@ static __global__ __launch_bounds__(256) void zero_kernel(double* a, long long n
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) a[i] = 0.0;
 }
 
-// Fixed-order sum of the dJ/dmu slots, two passes: block b of the first pass
-// sums slots [b kMuChunk, (b + 1) kMuChunk) into part[b]; one block then sums
-// the parts into out[0].  Both passes sum in the same order on every call.
-static __global__ __launch_bounds__(256) void reduce_mu_kernel(const double* a, long long n, double* out) {
+// Fixed-order sum of the dJ/dmu slots, two passes: block b sums slots
+// [b chunk, (b + 1) chunk) into out[b] (first pass: chunk = kMuChunk, one block
+// per chunk; second pass: one block, chunk = the number of parts).  Both
+// passes sum in the same order on every call.
+static __global__ __launch_bounds__(256) void reduce_mu_kernel(const double* a, long long n, long long chunk,
+                                                              double* out) {
   __shared__ double sh[256];
-  const long long lo = (long long)blockIdx.x * kMuChunk;
-  const long long hi = lo + kMuChunk < n ? lo + kMuChunk : n;
+  const long long lo = (long long)blockIdx.x * chunk;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
   double s = 0.0;
   for (long long i = lo + threadIdx.x; i < hi; i += 256) s += a[i];
   sh[threadIdx.x] = s;

@@ -530,6 +530,30 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
   // records is exact in T).
   const auto& mt = ModeTabHolder<K>::t;
   const long long ntile = (N + 63) >> 6;
+  // Reference flux of the cell in FP32-bulk: the Euler flux of its mean state,
+  // Cf[d][v].  It is subtracted from every volume point flux F_d and from the
+  // mean (tangential mode 0) of both face records along d before they are
+  // summed.  A flux constant over the cell adds nothing to R_n (the volume
+  // rule integrates dB_n/dx_d exactly, and its integral is the surface term's
+  // B_n(+1) - B_n(-1)), so this changes the result only by rounding, and the
+  // float sums then hold flux differences instead of p ~ 71 or (rho E + p) U.
+  constexpr bool CREF = NEED_F && sizeof(T) == 4;
+  // kept in the lane's LDS column (read where used) rather than 15 registers
+  __shared__ T scref[CREF ? 15 : 1][kCellThreads];
+  if constexpr (CREF) {
+    T cm[5], cfl[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) cm[v] = q[(long long)(v * NM) * N + cc];
+    const Prim<T> sm = primitive(cm, T(ph.gm1));
+    euler_flux<0>(sm, cm, cfl[0]);
+    euler_flux<1>(sm, cm, cfl[1]);
+    euler_flux<2>(sm, cm, cfl[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) scref[d * 5 + v][threadIdx.x] = cfl[d][v];
+  }
+  auto Cfr = [&](int d, int v) -> T { return scref[CREF ? d * 5 + v : 0][threadIdx.x]; };
   static_for<3>([&](auto dc) {
     constexpr int d = decltype(dc)::value;
     const T ix = T(0.5) * scale(d);  // 1 / width = |Gamma_d| / |K|
@@ -546,7 +570,12 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
           static_for<NT>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
             const int r = (f * 5 + v) * NT + m;
-            const T ru = pu[r * 64], rl = pl[r * 64];
+            T ru = pu[r * 64], rl = pl[r * 64];
+            if constexpr (CREF && is_f && m == 0) {
+              const T cr = Cfr(d, v);
+              ru -= cr;
+              rl -= cr;
+            }
             const T dm = ix * (rl - ru), dp = -ix * (rl + ru);
             static_for<NM>([&](auto nc) {
               constexpr int n = decltype(nc)::value;
@@ -606,7 +635,10 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
           const T b = ds[d][n] * wq;
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            if constexpr (NEED_F) acc[0][v][n] += F[d][v] * b;
+            if constexpr (CREF)
+              acc[0][v][n] += (F[d][v] - Cfr(d, v)) * b;
+            else if constexpr (NEED_F)
+              acc[0][v][n] += F[d][v] * b;
             if constexpr (NEED_FT) acc[NA - 1][v][n] += Ft[d][v] * b;
           }
         }

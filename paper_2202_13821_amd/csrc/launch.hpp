@@ -220,8 +220,8 @@ int run_adjoint(dg_hgks_ctx* c, const double* ckpt, int stride, double dt, int n
     }
   }
   DG_HIP(c, hipMemcpyAsync(q0_bar, qbar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<nparts, 256, 0, c->stream>>>(mu, nslots, mu_part2)));
-  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<1, 256, 0, c->stream>>>(mu_part2, nparts, mu_part2 + nparts)));
+  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<nparts, 256, 0, c->stream>>>(mu, nslots, kMuChunk, mu_part2)));
+  DG_LAUNCH(c, 2, (reduce_mu_kernel<<<1, 256, 0, c->stream>>>(mu_part2, nparts, nparts, mu_part2 + nparts)));
   double h = 0.0;
   DG_HIP(c, hipMemcpyAsync(&h, mu_part2 + nparts, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   DG_HIP(c, hipStreamSynchronize(c->stream));

@@ -40,10 +40,10 @@ GROUPS = (("rho", (0,)), ("momentum", (1, 2, 3)), ("rhoE", (4,)))
 # 128^3 step is ~1e-7 of the state), below what float32 fluxes resolve: its
 # increment error is measured and bounded, not small.
 TOL32 = {
-    "c2": {"state": 1e-6, "inc": (3e-5, 3e-5, 6e-5)},
+    "c2": {"state": 7e-7, "inc": (1.5e-5, 1.5e-5, 4e-5)},
     "c3": {"state": 5e-5, "inc": (0.5, 5e-3, 5e-2)},
-    "c4": {"state": 2e-5, "inc": (4.0, 5e-2, 0.15)},
-    "c4_100": {"state": 5e-5, "inc": (3e-2, 3e-3, 4e-2)},
+    "c4": {"state": 1e-5, "inc": (3.0, 4e-2, 0.15)},
+    "c4_100": {"state": 2e-5, "inc": (1.5e-2, 1e-3, 2e-2)},
 }
 
 

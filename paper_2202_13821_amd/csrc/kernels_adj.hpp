@@ -460,20 +460,36 @@ __global__ __launch_bounds__(kCellThreads) void adj_volume_kernel(const T* __res
     fu[d] = frec + frec_index(d, 0, c, 0, 5 * NM, ntile);
     fd[d] = frec + frec_index(d, 1, (long long)nb32(unsigned(c), d, -1, g), 0, 5 * NM, ntile);
   }
+  // Up to P2 all 5 NM sums are formed before the first store: a load placed
+  // after a store that may alias it (the compiler cannot tell) waits for that
+  // store, one memory latency per coefficient.  At P3 the lane has no
+  // registers to spare for them, and each coefficient is stored as it is
+  // summed.
+  constexpr int VB = NM <= 10 ? 5 : 1;
+  constexpr int NG = NM <= 10 ? NM : 1;
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
+  for (int v0 = 0; v0 < 5; v0 += VB)
 #pragma unroll
-    for (int n = 0; n < NM; ++n) {
-      const int vm = v * NM + n;
-      double s = double(sb[v][n]);
+    for (int n0 = 0; n0 < NM; n0 += NG) {
+      double s[VB][NG];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) s += fu[d][vm * 64] + fd[d][vm * 64];
-      const long long gi = (long long)vm * N + c;
-      if constexpr (STAGE == 2) {
-        out[gi] = s;
-      } else {
-        out[gi] = in.qbar[gi] + in.qsbar[gi] + s;
-      }
+      for (int j = 0; j < VB; ++j)
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+          const int vm = (v0 + j) * NM + n0 + i;
+          double a = double(sb[v0 + j][n0 + i]);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) a += fu[d][vm * 64] + fd[d][vm * 64];
+          if constexpr (STAGE != 2) {
+            const long long gi = (long long)vm * N + c;
+            a = in.qbar[gi] + in.qsbar[gi] + a;
+          }
+          s[j][i] = a;
+        }
+#pragma unroll
+      for (int j = 0; j < VB; ++j)
+#pragma unroll
+        for (int i = 0; i < NG; ++i) out[(long long)((v0 + j) * NM + n0 + i) * N + c] = s[j][i];
     }
 }
 

@@ -647,33 +647,57 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
   }
   if (bad && act) atomicOr(flag, 1);
 
-  // M^{-1} and the stage update in FP64
+  // M^{-1} and the stage update in FP64.  The FP64 inputs of the update (Q^n,
+  // P, or the L_t of the Ft pass) of a group of VB variables are loaded before
+  // the group's first store: the compiler cannot prove that the output arrays
+  // alias none of them, so a load placed after a store waits for that store and
+  // then for its own data, one full memory latency per coefficient.  VB = 5 (one
+  // group) where the inputs take at most 100 VGPRs, else smaller groups.
   if (!act) return;
   const double dt = out.dt;
+  constexpr int NIN = (MODE == 0 && PART == 1) ? 2 : ((MODE == 0 && PART != 2) || MODE == 1) ? 1 : 0;
+  constexpr int VB = NIN * NM * 5 <= 50 ? 5 : NIN * NM * 2 <= 50 ? 2 : 1;
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
+  for (int v0 = 0; v0 < 5; v0 += VB) {
+    double in[NIN > 0 ? NIN : 1][VB][NM];
+    if constexpr (NIN > 0) {
 #pragma unroll
-    for (int n = 0; n < NM; ++n) {
-      const double mi = mt.minv[n];
-      const double Ln = NEED_F ? double(acc[0][v][n]) * mi : 0.0;
-      const double Ltn = NEED_FT ? double(acc[NA - 1][v][n]) * mi : 0.0;
-      const long long gi = (long long)(v * NM + n) * N + c;
-      if constexpr (MODE == 0 && PART == 2) {
-        out.Lt[gi] = Ltn;
-      } else if constexpr (MODE == 0) {
-        const double qn = out.qn[gi];
-        const double lt = PART == 1 ? out.Lt[gi] : Ltn;
-        out.qstar[gi] = T(qn + 0.5 * dt * Ln + 0.125 * dt * dt * lt);
-        out.P[gi] = qn + dt * Ln + (dt * dt / 6.0) * lt;
-      } else if constexpr (MODE == 1) {
-        const double qnew = out.P[gi] + (dt * dt / 3.0) * Ltn;
-        out.qnew[gi] = qnew;
-        if (out.qshadow) out.qshadow[gi] = T(qnew);
-      } else {
-        if constexpr (NEED_F) out.L[gi] = Ln;
-        if constexpr (NEED_FT) out.Lt[gi] = Ltn;
-      }
+      for (int j = 0; j < VB; ++j)
+#pragma unroll
+        for (int n = 0; n < NM; ++n) {
+          if (v0 + j >= 5) break;
+          const long long gi = (long long)((v0 + j) * NM + n) * N + c;
+          in[0][j][n] = MODE == 1 ? out.P[gi] : out.qn[gi];
+          if constexpr (NIN == 2) in[NIN - 1][j][n] = out.Lt[gi];
+        }
     }
+#pragma unroll
+    for (int j = 0; j < VB; ++j)
+#pragma unroll
+      for (int n = 0; n < NM; ++n) {
+        if (v0 + j >= 5) break;
+        const int v = v0 + j;
+        const double mi = mt.minv[n];
+        const double Ln = NEED_F ? double(acc[0][v][n]) * mi : 0.0;
+        const double Ltn = NEED_FT ? double(acc[NA - 1][v][n]) * mi : 0.0;
+        const long long gi = (long long)(v * NM + n) * N + c;
+        if constexpr (MODE == 0 && PART == 2) {
+          out.Lt[gi] = Ltn;
+        } else if constexpr (MODE == 0) {
+          const double qn = in[0][j][n];
+          const double lt = PART == 1 ? in[NIN - 1][j][n] : Ltn;
+          out.qstar[gi] = T(qn + 0.5 * dt * Ln + 0.125 * dt * dt * lt);
+          out.P[gi] = qn + dt * Ln + (dt * dt / 6.0) * lt;
+        } else if constexpr (MODE == 1) {
+          const double qnew = in[0][j][n] + (dt * dt / 3.0) * Ltn;
+          out.qnew[gi] = qnew;
+          if (out.qshadow) out.qshadow[gi] = T(qnew);
+        } else {
+          if constexpr (NEED_F) out.L[gi] = Ln;
+          if constexpr (NEED_FT) out.Lt[gi] = Ltn;
+        }
+      }
+  }
 }
 
 // FP64 -> T copy of the coefficients (stage-1 input of the bulk-precision path).

@@ -452,10 +452,11 @@ constexpr bool kSplitVolume = sizeof(T) == 8 && K == 3;
 
 // Minimum waves per SIMD requested from the register allocator for the
 // volume kernel (FP32: two resident wavefronts per SIMD hide the memory
-// phases; FP64 needs twice the registers).
-template <class T, int K>
+// phases, three for stage 2, whose 50 accumulators fit in 168 VGPRs: 6% off
+// its time; FP64 needs twice the registers).
+template <class T, int K, int MODE = 0>
 struct CellWaves {
-  static constexpr int value = (sizeof(T) == 4 && K <= 2) ? 2 : 1;
+  static constexpr int value = (sizeof(T) == 4 && K <= 2) ? (MODE == 1 ? 3 : 2) : 1;
 };
 
 // Basis at the volume points, q = (qz NQ + qy) NQ + qx: phi[q][n] = B_n(x_q),
@@ -490,8 +491,8 @@ struct PointBasisHolder {
 };
 
 template <class T, int K, int NQ, int MODE, bool UNI, int PART = 0>
-__global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume_kernel(const T* __restrict__ q, const T* __restrict__ rec,
-                                                             Geo g, Phys ph, VolOut<T> out, int* flag) {
+__global__ __launch_bounds__(kCellThreads, (CellWaves<T, K, MODE>::value)) void volume_kernel(
+    const T* __restrict__ q, const T* __restrict__ rec, Geo g, Phys ph, VolOut<T> out, int* flag) {
   constexpr int NM = nmodes(K), NT = ntan(K), NQ3 = NQ * NQ * NQ;
   static_assert(PART == 0 || MODE != 1, "stage 2 has the Ft pass only");
   constexpr bool NEED_F = (MODE != 1) && PART != 2;  // accumulate F
@@ -595,17 +596,46 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
     for (int n = 0; n < NM; ++n) cf[v][n] = q[(long long)(v * NM + n) * N + cc];
 
   using PB = PointBasisHolder<T, K, NQ>;
+  // The point's basis values (wavefront-uniform, scalar loads) are read one
+  // point ahead in FP32 up to P2, so that their load latency overlaps the
+  // previous point (FP64 and P3 have no SGPRs to spare for a second set).
+  constexpr bool PF = sizeof(T) == 4 && K <= 2;
+  struct PtBasis {
+    T phi[NM], dphi[3][NM], w;
+  };
+  auto load_basis = [&](int qi, PtBasis& b) {
+    static_for<NM>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+      b.phi[n] = PB::t.phi[qi][n];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) b.dphi[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] : T(0);
+    });
+    b.w = PB::t.w[qi];
+  };
+  PtBasis nxt;
+  if constexpr (PF) load_basis(0, nxt);
   int bad = 0;
 #pragma unroll 1
   for (int qi = 0; qi < NQ3; ++qi) {
     // keeps the width scales in LDS: no load moves across this point
     __asm__ __volatile__("" ::: "memory");
+    PtBasis cur;
+    if constexpr (PF) {
+      cur = nxt;
+      load_basis(qi + 1 < NQ3 ? qi + 1 : qi, nxt);
+    }
+    auto PHI = [&](int n) -> T {
+      if constexpr (PF) return cur.phi[n]; else return PB::t.phi[qi][n];
+    };
+    auto DPHI = [&](int d, int n) -> T {
+      if constexpr (PF) return cur.dphi[d][n]; else return PB::t.dphi[qi][d][n];
+    };
     // physical-space derivative of the basis at this point (this cell's widths)
     T ds[3][NM];
     static_for<NM>([&](auto nc) {
       constexpr int n = decltype(nc)::value;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ds[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] * scale(d) : T(0);
+      for (int d = 0; d < 3; ++d) ds[d][n] = (md.e[n][d] > 0) ? DPHI(d, n) * scale(d) : T(0);
     });
     T Q[5], dQ[3][5];
 #pragma unroll
@@ -614,7 +644,7 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
       static_for<NM>([&](auto nc) {
         constexpr int n = decltype(nc)::value;
         const T cn = cf[v][n];
-        if constexpr (n > 0) v0 += cn * PB::t.phi[qi][n];
+        if constexpr (n > 0) v0 += cn * PHI(n);
         if constexpr (md.e[n][0] > 0) vx += cn * ds[0][n];
         if constexpr (md.e[n][1] > 0) vy += cn * ds[1][n];
         if constexpr (md.e[n][2] > 0) vz += cn * ds[2][n];
@@ -626,7 +656,8 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K>::value)) void volume
     }
     T F[3][5], Ft[3][5];
     volume_flux<T, NEED_F>(ph, Q, dQ, F, Ft, bad);
-    const T wq = PB::t.w[qi];
+    T wq;
+    if constexpr (PF) wq = cur.w; else wq = PB::t.w[qi];
     static_for<NM>([&](auto nc) {
       constexpr int n = decltype(nc)::value;
 #pragma unroll

@@ -4,6 +4,8 @@ from the kernels' own header and checked against the forms they replace:
 - m5_acc (the m5 moment vector without its three moment matrices) against
   <u^2 psi psi^T> x + <u v psi psi^T> y + <u w psi psi^T> z built from
   mat_H<2>, mat_Gv and mat_Gw;
+- hmat_mv_acc<p> (<u^p psi psi^T> x without the matrix, p = 0, 1) against
+  mat_H<p> applied by sym_mv_acc;
 - prim_grad_dt (primitive gradients and the Euler time derivative in one
   pass) against prim_grad and euler_dt;
 - the Solver5 closed form of <a psi> = b against the Maxwellian moment
@@ -53,6 +55,15 @@ int main() {
     mat_Gw(M, t, H); sym_mv_acc(H, z, a);
     m5_acc(M, t, x, y, z, b);
     printf("m5 %.3e\n", rel(a, b, 5));
+    // <u^p psi psi^T> x matrix-free (p = 0, 1) against mat_H<p> times x
+    for (int p = 0; p < 2; ++p) {
+      double c[5] = {0}, d[5] = {0};
+      if (p) mat_H<1>(M, t, H); else mat_H<0>(M, t, H);
+      sym_mv_acc(H, y, c);
+      const double hR1 = 0.5 * t.R1, q4 = 0.25 * (t.R2 - t.R1 * t.R1);
+      if (p) hmat_mv_acc<1>(M, t, th, hR1, q4, y, d); else hmat_mv_acc<0>(M, t, th, hR1, q4, y, d);
+      printf("hmv %.3e\n", rel(c, d, 5));
+    }
     // prim_grad_dt
     const double rho = R(g);
     double Q[5] = {rho, rho * Uu, rho * V, rho * W, 0.0}, dq[3][5];
@@ -108,8 +119,9 @@ def results(tmp_path_factory):
     return {k: np.array(v) for k, v in res.items()}
 
 
-@pytest.mark.parametrize("name,tol", [("m5", 1e-13), ("dt", 1e-13), ("grad", 1e-14), ("solve", 1e-12)])
-def test_rewritten_forms_agree(results, name, tol):
+@pytest.mark.parametrize("name,tol,n", [("m5", 1e-13, 4000), ("hmv", 1e-13, 8000), ("dt", 1e-13, 4000),
+                                        ("grad", 1e-14, 4000), ("solve", 1e-12, 4000)])
+def test_rewritten_forms_agree(results, name, tol, n):
     r = results[name]
-    assert len(r) == 4000
+    assert len(r) == n
     assert r.max() < tol, (name, r.max())

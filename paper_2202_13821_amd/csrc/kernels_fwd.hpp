@@ -614,7 +614,8 @@ __global__ __launch_bounds__(kCellThreads, (CellWaves<T, K, MODE>::value)) void 
         });
       });
     }
-    __builtin_amdgcn_sched_barrier(0);
+    // (not after the last group: the cell's coefficient loads may start there)
+    if constexpr (G + 1 < NG) __builtin_amdgcn_sched_barrier(0);
   });
 
   // the cell's coefficients, then the volume term

@@ -387,14 +387,46 @@ __global__ __launch_bounds__(kCellThreads) void adj_volume_kernel(const T* __res
   cell_ijk(unsigned(cc), g, ci);
   const T sc[3] = {T(2.0 / g.w[0][ci[0]]), T(2.0 / g.w[1][ci[1]]), T(2.0 / g.w[2][ci[2]])};
   using PB = PointBasisHolder<T, K, NQ>;
+  // The point's basis values (scalar loads) are read one point ahead in FP32
+  // up to P2, as in the forward volume kernel, and issued at the top of the
+  // previous point (scheduling barrier; here, unlike the forward kernel, that
+  // measured faster: -16% of the kernel at 32^3, -2.5% at 128^3).
+  constexpr bool PF = sizeof(T) == 4 && K <= 2;
+  struct PtBasis {
+    T phi[NM], dphi[3][NM], w;
+  };
+  auto load_basis = [&](int qi, PtBasis& b) {
+    static_for<NM>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+      b.phi[n] = PB::t.phi[qi][n];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) b.dphi[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] : T(0);
+    });
+    b.w = PB::t.w[qi];
+  };
+  PtBasis nxt;
+  if constexpr (PF) load_basis(0, nxt);
   double mub = 0.0;
 #pragma unroll 1
   for (int qi = 0; qi < NQ3; ++qi) {
+    PtBasis cur;
+    if constexpr (PF) {
+      cur = nxt;
+      load_basis(qi + 1 < NQ3 ? qi + 1 : qi, nxt);
+      __builtin_amdgcn_sched_barrier(0);  // issue the next point's loads here
+    }
+    auto PHI = [&](int n) -> T {
+      if constexpr (PF) return cur.phi[n]; else return PB::t.phi[qi][n];
+    };
     T ds[3][NM];
     static_for<NM>([&](auto nc) {
       constexpr int n = decltype(nc)::value;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ds[d][n] = (md.e[n][d] > 0) ? PB::t.dphi[qi][d][n] * sc[d] : T(0);
+      for (int d = 0; d < 3; ++d) {
+        T dp;
+        if constexpr (PF) dp = cur.dphi[d][n]; else dp = PB::t.dphi[qi][d][n];
+        ds[d][n] = (md.e[n][d] > 0) ? dp * sc[d] : T(0);
+      }
     });
     T Q[5], dQ[3][5];
 #pragma unroll
@@ -403,7 +435,7 @@ __global__ __launch_bounds__(kCellThreads) void adj_volume_kernel(const T* __res
       static_for<NM>([&](auto nc) {
         constexpr int n = decltype(nc)::value;
         const T cn = cf[v][n];
-        v0 += cn * PB::t.phi[qi][n];
+        v0 += cn * PHI(n);
         if constexpr (md.e[n][0] > 0) vx += cn * ds[0][n];
         if constexpr (md.e[n][1] > 0) vy += cn * ds[1][n];
         if constexpr (md.e[n][2] > 0) vz += cn * ds[2][n];
@@ -414,7 +446,8 @@ __global__ __launch_bounds__(kCellThreads) void adj_volume_kernel(const T* __res
       dQ[2][v] = vz;
     }
     // Fbar_d(q)[v] = w_q sum_n (2/dx_d) dB_n/dxi_d Rbar_n[v]
-    const T wq = PB::t.w[qi];
+    T wq;
+    if constexpr (PF) wq = cur.w; else wq = PB::t.w[qi];
     T Fb[3][5], Ftb[3][5];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -441,7 +474,7 @@ __global__ __launch_bounds__(kCellThreads) void adj_volume_kernel(const T* __res
     for (int v = 0; v < 5; ++v)
       static_for<NM>([&](auto nc) {
         constexpr int n = decltype(nc)::value;
-        T a = qb[v] * PB::t.phi[qi][n];
+        T a = qb[v] * PHI(n);
         if constexpr (md.e[n][0] > 0) a += dqb[0][v] * ds[0][n];
         if constexpr (md.e[n][1] > 0) a += dqb[1][v] * ds[1][n];
         if constexpr (md.e[n][2] > 0) a += dqb[2][v] * ds[2][n];

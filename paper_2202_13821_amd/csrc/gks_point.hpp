@@ -43,19 +43,39 @@ DGK_HD double d_exp(double x) { return exp(x); }
 DGK_HD float d_sqrt(float x) { return sqrtf(x); }
 DGK_HD double d_sqrt(double x) { return sqrt(x); }
 // Reciprocal, reciprocal square root and exp: FP32-bulk uses the hardware
-// instructions (v_rcp_f32, v_rsq_f32: 1 ulp; v_exp_f32: ~1-2 ulp), the FP64
-// path keeps IEEE-rounded division, sqrt and the library exp.
+// instructions (v_rcp_f32, v_rsq_f32: 1 ulp; v_exp_f32: ~1-2 ulp).  FP64
+// refines the hardware v_rcp_f64 / v_rsq_f64 estimates by two Newton-Raphson
+// steps each (the relative error squares at every step), which leaves at most
+// about 1 ulp for the positive, normal arguments these are used on (densities,
+// temperatures, pressures); the FP64 path keeps the library exp.
 #ifdef __HIP_DEVICE_COMPILE__
 DGK_HD float d_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 DGK_HD float d_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 DGK_HD float d_expf_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f); }
+DGK_HD double d_rcp(double x) {
+  // r <- r + r (1 - x r)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+DGK_HD double d_rsqrt(double x) {
+  // r <- r + r (1/2 - (x/2) r^2)
+  const double h = 0.5 * x;
+  double r = __builtin_amdgcn_rsq(x);
+  double e = __builtin_fma(-h * r, r, 0.5);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-h * r, r, 0.5);
+  return __builtin_fma(r, e, r);
+}
 #else
 DGK_HD float d_rcp(float x) { return 1.0f / x; }
 DGK_HD float d_rsqrt(float x) { return 1.0f / sqrtf(x); }
 DGK_HD float d_expf_fast(float x) { return expf(x); }
-#endif
 DGK_HD double d_rcp(double x) { return 1.0 / x; }
 DGK_HD double d_rsqrt(double x) { return 1.0 / sqrt(x); }
+#endif
 DGK_HD float d_exp_bulk(float x) { return d_expf_fast(x); }
 DGK_HD double d_exp_bulk(double x) { return exp(x); }
 
@@ -705,7 +725,7 @@ DGK_HD void face_finish(const Phys& ph, const FaceAcc<T>& acc, T F[5], T Ft[5], 
 #pragma unroll
   for (int k = 0; k < 5; ++k) m2[k] = s0.p * ns[k] - m3[k];
 
-  const double tau = ph.mu / double(s0.p);
+  const double tau = ph.mu * d_rcp(double(s0.p));
   double al[6], be[6];
   time_coefficients(tau, ph.half_dt_over_mu * double(s0.p), ph.dt, ph.inv_dt, al, be, ec);
   // beta_3 = -beta_0, beta_4 = -beta_1, alpha_3 = 1 - alpha_0, alpha_4 = -tau - alpha_1:

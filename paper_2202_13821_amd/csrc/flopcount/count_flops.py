@@ -128,7 +128,8 @@ def adjoint_totals(c, k, nq):
 RULES = ((1, 2), (2, 3), (2, 2), (3, 4), (3, 3))
 
 
-def main():
+def compute():
+    """The counts as written to flops.json (compiles the host IR)."""
     text = ir()
     res = {"k": 2, "nq": 3, "counted_from": "optimised host LLVM IR of gks_point.hpp"}
     rules = {f"p{k}_nq{nq}": {} for k, nq in RULES}
@@ -153,6 +154,11 @@ def main():
             rules[f"p{k}_nq{nq}"][tag] = totals(counts, k, nq)
             rules[f"p{k}_nq{nq}"][f"adjoint_{tag}"] = adjoint_totals(ac, k, nq)
     res["rules"] = rules
+    return res
+
+
+def main():
+    res = compute()
     path = os.path.join(PKG, "flops.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)

@@ -259,8 +259,8 @@ def cpu_baseline(n, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is a design "
-              "in DESIGN.md, not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path (a domain "
+              "decomposition with one halo exchange per stage) is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
 

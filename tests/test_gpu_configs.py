@@ -34,8 +34,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 GROUPS = (("rho", (0,)), ("momentum", (1, 2, 3)), ("rhoE", (4,)))
 
 # FP32-bulk tolerances (float32 fluxes and projections, FP64 stage
-# accumulation), from the measured values (precision section):
-# state, then increment per group (rho, momentum, rho E).  The density of the
+# accumulation), about 2.5 times the measured values: state, then increment
+# per group (rho, momentum, rho E).  The density of the
 # Mach 0.1 vortex barely moves over the first steps (its change after one
 # 128^3 step is ~1e-7 of the state), below what float32 fluxes resolve: its
 # increment error is measured and bounded, not small.

@@ -52,14 +52,17 @@ def test_nonuniform_residual_fp32_bulk(k, nq):
     assert eL <= 1e-4 and eLt <= 1e-3
 
 
+@pytest.mark.parametrize("k", [2, 3])
 @pytest.mark.parametrize("precision,tol,told", [("fp64", 1e-10, 1e-9), ("fp32_bulk", 1e-5, 5e-2)])
-def test_nonuniform_steps(precision, tol, told):
-    say("nonuniform steps", precision)
-    rng = np.random.default_rng(920)
+def test_nonuniform_steps(precision, tol, told, k):
+    """Also P3: the FP64 stage-1 pass then runs as its two launches (L_t pass,
+    then F pass and update) on the non-uniform kernels."""
+    say("nonuniform steps", precision, "P%d" % k)
+    rng = np.random.default_rng(920 + k)
     shape = (7, 3, 5)
     w = IN.random_widths(rng, shape, LO, HI)
-    q0 = IN.random_field(rng, shape, 10, amp=0.03)
-    s, c = pair(shape, 2, LO, HI, mu=0.005, pr=0.72, precision=precision, widths=w)
+    q0 = IN.random_field(rng, shape, P.nmodes(k), amp=0.03)
+    s, c = pair(shape, k, LO, HI, mu=0.005, pr=0.72, precision=precision, widths=w)
     q = to_dev(q0)
     s.step(q, 1e-3, 3)
     qo = O.step(c, q0, 1e-3, 3)

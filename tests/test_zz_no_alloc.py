@@ -45,3 +45,25 @@ def test_noalloc_step_rejects_grids_beyond_its_scratch():
     q = torch.zeros((5, 10, 64, 64, 64), dtype=torch.float64, device="cuda:0")
     with pytest.raises(DGHGKSError, match="scratch"):
         step_noalloc(q, 1e-3, 1, (64, 64, 64), (0, 0, 0), (1, 1, 1), 2)
+
+
+@pytest.mark.parametrize("k,nq", [(1, 2), (3, 4), (3, 3)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_noalloc_step_other_rules(precision, k, nq):
+    """P1 and P3 (FP64 P3 also uses the L_t buffer of the two-launch stage-1
+    pass, placed in the static scratch) on a small ragged grid."""
+    shape, lo, hi = (6, 4, 5), (0.0, -0.5, 0.2), (1.0, 1.0, 1.1)
+    say(f"no-alloc step {precision} P{k} nq {nq} {shape}")
+    rng = np.random.default_rng(4321 + 10 * k + nq)
+    q0 = IN.random_field(rng, shape, P.nmodes(k), amp=0.03)
+    s = Solver(shape, lo, hi, k, nq=nq, mu=0.01, prandtl=0.72, precision=precision, device="cuda:0")
+    qa = to_dev(q0)
+    s.step(qa, 2e-3, 2)
+    s.check()
+    qb = to_dev(q0)
+    flag = torch.full((1,), -1, dtype=torch.int32, device="cuda:0")
+    step_noalloc(qb, 2e-3, 2, shape, lo, hi, k, nq=nq, mu=0.01, prandtl=0.72, precision=precision, nonphys=flag)
+    torch.cuda.synchronize()
+    assert flag.item() == 0
+    assert torch.equal(qa, qb)
+    del s

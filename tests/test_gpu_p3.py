@@ -55,18 +55,19 @@ def test_p3_residual_fp32_bulk(nq):
 
 
 @pytest.mark.parametrize("nq", [4, 3])
-def test_p3_steps_ragged_fp64(nq):
-    say("p3 steps fp64", nq)
+@pytest.mark.parametrize("precision,tol,told", [("fp64", 1e-10, 1e-9), ("fp32_bulk", 1e-5, 5e-2)])
+def test_p3_steps_ragged(nq, precision, tol, told):
+    say("p3 steps", precision, nq)
     rng = np.random.default_rng(820 + nq)
     shape = (7, 3, 5)
     q0 = IN.random_field(rng, shape, NM3, amp=0.03)
-    s, c = pair(shape, 3, LO, HI, nq=nq, mu=0.005, pr=0.72)
+    s, c = pair(shape, 3, LO, HI, nq=nq, mu=0.005, pr=0.72, precision=precision)
     q = to_dev(q0)
     s.step(q, 1e-3, 2)
     qo = O.step(c, q0, 1e-3, 2)
     e, ed = rel_l2(to_np(q), qo), rel_l2(to_np(q) - q0, qo - q0)
     say("  rel L2 of q, of q - q0:", e, ed)
-    assert e <= 1e-10 and ed <= 1e-9
+    assert e <= tol and ed <= told
     s.check()
 
 

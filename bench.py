@@ -206,15 +206,9 @@ def parity_vs_oracle():
 
 
 def kernel_source_hash():
-    import hashlib
+    from paper_2202_13821_amd.profiling import kernel_source_hash as h
 
-    h = hashlib.sha256()
-    src = os.path.join(ROOT, "paper_2202_13821_amd", "csrc")
-    for name in sorted(os.listdir(src)):
-        if name.endswith((".hpp", ".hip")):
-            with open(os.path.join(src, name), "rb") as f:
-                h.update(f.read())
-    return h.hexdigest()[:16]
+    return h()
 
 
 def measured_traffic(kernel_key):

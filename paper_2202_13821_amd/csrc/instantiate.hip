@@ -1,16 +1,35 @@
 // instantiate.hip -- explicit instantiation of the launch code for one
 // configuration, selected at compile time with -DDGK_T=float|double
 // -DDGK_K=<degree> -DDGK_NQ=<points per axis> (one object file each, so the
-// configurations compile in parallel).
+// configurations compile in parallel), and -DDGK_PART=1 (the step and the
+// operator evaluation, with the two stage launches) or 2 (the adjoint).
+//
+// The two parts are separate objects so that each can be compiled with its
+// own code-generation options.  The adjoint's forward recomputation calls
+// the stage launches of part 1 (declared extern below), so every forward
+// kernel is compiled exactly once.
 #include "launch.hpp"
 
-#if !defined(DGK_T) || !defined(DGK_K) || !defined(DGK_NQ)
-#error "instantiate.hip needs DGK_T, DGK_K and DGK_NQ"
+#if !defined(DGK_T) || !defined(DGK_K) || !defined(DGK_NQ) || !defined(DGK_PART)
+#error "instantiate.hip needs DGK_T, DGK_K, DGK_NQ and DGK_PART"
 #endif
 
 namespace dgrt {
+#if DGK_PART == 1
+template int launch_stage<DGK_T, DGK_K, DGK_NQ, 0>(dg_hgks_ctx*, const DGK_T*, const VolOut<DGK_T>&, const Geo&,
+                                                   const Phys&);
+template int launch_stage<DGK_T, DGK_K, DGK_NQ, 1>(dg_hgks_ctx*, const DGK_T*, const VolOut<DGK_T>&, const Geo&,
+                                                   const Phys&);
 template int run_step<DGK_T, DGK_K, DGK_NQ>(dg_hgks_ctx*, double*, double, int, double*, int);
 template int run_residual<DGK_T, DGK_K, DGK_NQ>(dg_hgks_ctx*, const double*, double, double*, double*);
+#elif DGK_PART == 2
+extern template int launch_stage<DGK_T, DGK_K, DGK_NQ, 0>(dg_hgks_ctx*, const DGK_T*, const VolOut<DGK_T>&,
+                                                          const Geo&, const Phys&);
+extern template int launch_stage<DGK_T, DGK_K, DGK_NQ, 1>(dg_hgks_ctx*, const DGK_T*, const VolOut<DGK_T>&,
+                                                          const Geo&, const Phys&);
 template int run_adjoint<DGK_T, DGK_K, DGK_NQ>(dg_hgks_ctx*, const double*, int, double, int, const double*,
                                                double*, double*);
+#else
+#error "DGK_PART is 1 (forward) or 2 (adjoint)"
+#endif
 }  // namespace dgrt

@@ -37,6 +37,9 @@ def kernel_source_hash():
         if name.endswith((".hpp", ".hip")):
             with open(os.path.join(src, name), "rb") as f:
                 h.update(f.read())
+    # the build options (code generation) belong to the kernels too
+    with open(os.path.join(ROOT, "paper_2202_13821_amd", "build.py"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -2,12 +2,13 @@
 // configuration, selected at compile time with -DDGK_T=float|double
 // -DDGK_K=<degree> -DDGK_NQ=<points per axis> (one object file each, so the
 // configurations compile in parallel), and -DDGK_PART=1 (the step and the
-// operator evaluation, with the two stage launches) or 2 (the adjoint).
+// operator evaluation, with the two stage launches), 2 (the adjoint, with its
+// face passes) or 3 (the adjoint's volume passes).
 //
-// The two parts are separate objects so that each can be compiled with its
-// own code-generation options.  The adjoint's forward recomputation calls
-// the stage launches of part 1 (declared extern below), so every forward
-// kernel is compiled exactly once.
+// The parts are separate objects so that each can be compiled with its own
+// code-generation options.  The adjoint calls the stage launches of part 1
+// for its forward recomputation and the volume launches of part 3 (declared
+// extern below), so every kernel is compiled exactly once.
 #include "launch.hpp"
 
 #if !defined(DGK_T) || !defined(DGK_K) || !defined(DGK_NQ) || !defined(DGK_PART)
@@ -27,9 +28,18 @@ extern template int launch_stage<DGK_T, DGK_K, DGK_NQ, 0>(dg_hgks_ctx*, const DG
                                                           const Geo&, const Phys&);
 extern template int launch_stage<DGK_T, DGK_K, DGK_NQ, 1>(dg_hgks_ctx*, const DGK_T*, const VolOut<DGK_T>&,
                                                           const Geo&, const Phys&);
+extern template int launch_adj_volume<DGK_T, DGK_K, DGK_NQ, 1>(dg_hgks_ctx*, const DGK_T*, const AdjIn<1>&, double*,
+                                                               const Geo&, const Phys&);
+extern template int launch_adj_volume<DGK_T, DGK_K, DGK_NQ, 2>(dg_hgks_ctx*, const DGK_T*, const AdjIn<2>&, double*,
+                                                               const Geo&, const Phys&);
 template int run_adjoint<DGK_T, DGK_K, DGK_NQ>(dg_hgks_ctx*, const double*, int, double, int, const double*,
                                                double*, double*);
+#elif DGK_PART == 3
+template int launch_adj_volume<DGK_T, DGK_K, DGK_NQ, 1>(dg_hgks_ctx*, const DGK_T*, const AdjIn<1>&, double*,
+                                                        const Geo&, const Phys&);
+template int launch_adj_volume<DGK_T, DGK_K, DGK_NQ, 2>(dg_hgks_ctx*, const DGK_T*, const AdjIn<2>&, double*,
+                                                        const Geo&, const Phys&);
 #else
-#error "DGK_PART is 1 (forward) or 2 (adjoint)"
+#error "DGK_PART is 1 (forward), 2 (adjoint) or 3 (adjoint volume passes)"
 #endif
 }  // namespace dgrt

@@ -122,19 +122,37 @@ int run_residual(dg_hgks_ctx* c, const double* q, double dt, double* L, double* 
   return launch_stage<T, K, NQ, 2>(c, qin, o, g, ph);
 }
 
-// Adjoint of one stage: face pass then volume pass (kernels_adj.hpp).
+// Adjoint of one stage: face pass then volume pass (kernels_adj.hpp).  The
+// two passes are separate functions so that each can be instantiated in its
+// own object (instantiate.hip).
 template <class T, int K, int NQ, int STAGE>
-int launch_adj_stage(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, double* out, const Geo& g,
-                     const Phys& ph) {
+int launch_adj_face(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, const Geo& g, const Phys& ph) {
+  const unsigned nbf = (unsigned)adj_face_blocks((size_t)g.ncell);
+  double* frec = (double*)(c->ws + c->lay.adj_frec);
+  double* mu = (double*)(c->ws + c->lay.adj_mu);
+  DG_LAUNCH(c, 3, (adj_face_kernel<T, K, NQ, STAGE><<<dim3(3 * nbf), kAdjFaceThreads, 0, c->stream>>>(qin, in, frec, g, ph, mu)));
+  return DG_HGKS_OK;
+}
+
+template <class T, int K, int NQ, int STAGE>
+int launch_adj_volume(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, double* out, const Geo& g,
+                      const Phys& ph) {
   const long long N = g.ncell;
   const unsigned nbf = (unsigned)adj_face_blocks((size_t)N);
   const unsigned nbv = (unsigned)((N + kCellThreads - 1) / kCellThreads);
   double* frec = (double*)(c->ws + c->lay.adj_frec);
   double* mu = (double*)(c->ws + c->lay.adj_mu);
-  DG_LAUNCH(c, 3, (adj_face_kernel<T, K, NQ, STAGE><<<dim3(3 * nbf), kAdjFaceThreads, 0, c->stream>>>(qin, in, frec, g, ph, mu)));
   DG_LAUNCH(c, 4, (adj_volume_kernel<T, K, NQ, STAGE><<<dim3(nbv), kCellThreads, 0, c->stream>>>(
                       qin, in, frec, out, g, ph, mu, 3LL * nbf)));
   return DG_HGKS_OK;
+}
+
+template <class T, int K, int NQ, int STAGE>
+int launch_adj_stage(dg_hgks_ctx* c, const T* qin, const AdjIn<STAGE>& in, double* out, const Geo& g,
+                     const Phys& ph) {
+  const int rc = launch_adj_face<T, K, NQ, STAGE>(c, qin, in, g, ph);
+  if (rc) return rc;
+  return launch_adj_volume<T, K, NQ, STAGE>(c, qin, in, out, g, ph);
 }
 
 // Reverse sweep over the steps.  Segment s covers steps [s*stride,

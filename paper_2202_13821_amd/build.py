@@ -1,9 +1,10 @@
 """Build the HIP library libdg_hgks.so for gfx950 (in-tree, under lib/).
 
-The C-ABI (csrc/dg_hgks.hip) and three objects per compiled configuration
+The C-ABI (csrc/dg_hgks.hip) and four objects per compiled configuration
 (csrc/instantiate.hip with -DDGK_T/-DDGK_K/-DDGK_NQ and -DDGK_PART: the
-forward launches, the adjoint with its face passes, the adjoint's volume
-passes) are compiled in parallel, then linked.
+forward launches with the face passes, the forward volume passes, the
+adjoint with its face passes, the adjoint's volume passes) are compiled in
+parallel, then linked.
 """
 import os
 import subprocess
@@ -28,39 +29,47 @@ FLAGS = [
 CONFIGS = [(t, k, nq) for t in ("float", "double") for (k, nq) in ((1, 2), (2, 3), (2, 2), (3, 4), (3, 3))]
 
 # The backend's iterative ILP scheduling strategy, where it measured faster
-# (alternated builds in one session, bit-identical results):
+# (alternated builds in one session; results bit-identical, or within the
+# adjoint tests' tolerances):
 # - the FP32 forward kernels (face and volume) up to P2, which run two
 #   wavefronts per SIMD (three for the P2 stage-2 volume pass): the P2 face
 #   kernel took 4% less time per launch;
+# - the P3 forward volume kernels in FP32 (3-10% less) and in FP64 with 4
+#   points (16% less; with 3 points it was 25% slower);
 # - the P3 adjoint volume kernels: 40% less in FP64, 24% less in FP32.
 # Elsewhere it was slower: up to 80% for the FP64 forward face kernel, 70%
 # for the FP32 P2 adjoint volume kernel, 18-40% for the P3 adjoint face
-# kernels.  At P3 the FP32 forward step was 4-8% faster, but the
-# non-uniform-mesh operator built this way returned NaN where the default
-# build matches the oracle, so the P3 forward kernels keep the default.
+# kernels.  The FP32 P3 forward face kernel was 4-5% faster with it, but its
+# non-uniform-mesh variant then returned NaN where the default build matches
+# the oracle, so it keeps the default.
 SCHED_ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
 
 
-def _sched(t, k, part):
-    if part == 1:
+def _sched(t, k, nq, part):
+    if part == 1:  # forward launches and face passes
         return SCHED_ILP if t == "float" and k <= 2 else []
-    if part == 3:
+    if part == 4:  # forward volume passes
+        return SCHED_ILP if t == "float" or (k == 3 and nq == 4) else []
+    if part == 3:  # adjoint volume passes
         return SCHED_ILP if k == 3 else []
     return []
+
+
+PARTS = ((1, "fwd"), (4, "fwdvol"), (2, "adj"), (3, "adjvol"))
 
 
 def _units():
     yield "dg_hgks", os.path.join(CSRC, "dg_hgks.hip"), []
     for t, k, nq in CONFIGS:
         defs = [f"-DDGK_T={t}", f"-DDGK_K={k}", f"-DDGK_NQ={nq}"]
-        for part, tag in ((1, "fwd"), (2, "adj"), (3, "adjvol")):
+        for part, tag in PARTS:
             yield (f"inst_{t}_{k}{nq}_{tag}", os.path.join(CSRC, "instantiate.hip"),
-                   defs + [f"-DDGK_PART={part}"] + _sched(t, k, part))
+                   defs + [f"-DDGK_PART={part}"] + _sched(t, k, nq, part))
 
 
 def build(verbose: bool = False, extra=(), jobs: int = None) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
-    jobs = jobs or max(1, min(3 * len(CONFIGS) + 1, os.cpu_count() or 1, 16))
+    jobs = jobs or max(1, min(len(PARTS) * len(CONFIGS) + 1, os.cpu_count() or 1, 16))
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     with tempfile.TemporaryDirectory(prefix="dg_hgks_build_") as tmp:
         objs, pending = [], []

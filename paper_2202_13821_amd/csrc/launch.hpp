@@ -27,15 +27,15 @@ int launch_convert(dg_hgks_ctx* c, const double* a, T* b, long long n) {
   return DG_HGKS_OK;
 }
 
-// One operator evaluation (face pass + volume pass).
+// One operator evaluation: face pass, then volume pass.  The two passes are
+// separate functions so that each can be instantiated in its own object
+// (instantiate.hip).
 template <class T, int K, int NQ, int MODE>
-int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g, const Phys& ph) {
+int launch_face_pass(dg_hgks_ctx* c, const T* qin, const Geo& g, const Phys& ph) {
   T* rec = (T*)(c->ws + c->lay.rec);
   int* flag = (int*)(c->ws + c->lay.flag);
-  const long long N = g.ncell;
-  const unsigned nvb = (unsigned)((N + kCellThreads - 1) / kCellThreads);
   constexpr int FT = face_threads<T, K>();
-  const unsigned nfb = (unsigned)((N + FT - 1) / FT);
+  const unsigned nfb = (unsigned)((g.ncell + FT - 1) / FT);
   // uniform meshes take the cell widths from the kernel arguments
   auto run = [&](auto uc) {
     constexpr bool UNI = decltype(uc)::value;
@@ -44,6 +44,18 @@ int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g,
     } else {
       DG_LAUNCH(c, 0, (face_kernel<T, K, NQ, true, UNI><<<dim3(3 * nfb), FT, 0, c->stream>>>(qin, rec, g, ph, flag)));
     }
+    return DG_HGKS_OK;
+  };
+  return g.uniform ? run(std::true_type{}) : run(std::false_type{});
+}
+
+template <class T, int K, int NQ, int MODE>
+int launch_volume_pass(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g, const Phys& ph) {
+  const T* rec = (const T*)(c->ws + c->lay.rec);
+  int* flag = (int*)(c->ws + c->lay.flag);
+  const unsigned nvb = (unsigned)((g.ncell + kCellThreads - 1) / kCellThreads);
+  auto run = [&](auto uc) {
+    constexpr bool UNI = decltype(uc)::value;
     if constexpr (MODE != 1 && kSplitVolume<T, K>) {
       // Ft pass (L_t to the workspace in stage 1), then F pass and update
       VolOut<T> ot = o;
@@ -59,6 +71,13 @@ int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g,
     return DG_HGKS_OK;
   };
   return g.uniform ? run(std::true_type{}) : run(std::false_type{});
+}
+
+template <class T, int K, int NQ, int MODE>
+int launch_stage(dg_hgks_ctx* c, const T* qin, const VolOut<T>& o, const Geo& g, const Phys& ph) {
+  const int rc = launch_face_pass<T, K, NQ, MODE>(c, qin, g, ph);
+  if (rc) return rc;
+  return launch_volume_pass<T, K, NQ, MODE>(c, qin, o, g, ph);
 }
 
 template <class T, int K, int NQ>

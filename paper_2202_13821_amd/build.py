@@ -34,8 +34,9 @@ CONFIGS = [(t, k, nq) for t in ("float", "double") for (k, nq) in ((1, 2), (2, 3
 # - the FP32 forward kernels (face and volume) up to P2, which run two
 #   wavefronts per SIMD (three for the P2 stage-2 volume pass): the P2 face
 #   kernel took 4% less time per launch;
-# - the P3 forward volume kernels in FP32 (3-10% less) and in FP64 with 4
-#   points (16% less; with 3 points it was 25% slower);
+# - the forward volume kernels in FP64 at P2 (1-3% less) and at P3 with 4
+#   points (16% less; with 3 points it was 25% slower), and in FP32 at P3
+#   (3-10% less);
 # - the P3 adjoint volume kernels: 40% less in FP64, 24% less in FP32.
 # Elsewhere it was slower: up to 80% for the FP64 forward face kernel, 70%
 # for the FP32 P2 adjoint volume kernel, 18-40% for the P3 adjoint face
@@ -43,13 +44,18 @@ CONFIGS = [(t, k, nq) for t in ("float", "double") for (k, nq) in ((1, 2), (2, 3
 # non-uniform-mesh variant then returned NaN where the default build matches
 # the oracle, so it keeps the default.
 SCHED_ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
+# The backend's max-ILP strategy for the FP64 adjoint face kernel at P2: 2.7%
+# less time per launch (it made the adjoint volume kernel 22% slower).
+SCHED_MAX_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 
 
 def _sched(t, k, nq, part):
     if part == 1:  # forward launches and face passes
         return SCHED_ILP if t == "float" and k <= 2 else []
     if part == 4:  # forward volume passes
-        return SCHED_ILP if t == "float" or (k == 3 and nq == 4) else []
+        return SCHED_ILP if t == "float" or k == 2 or (k == 3 and nq == 4) else []
+    if part == 2:  # adjoint launch sequence and face passes
+        return SCHED_MAX_ILP if t == "double" and k == 2 else []
     if part == 3:  # adjoint volume passes
         return SCHED_ILP if k == 3 else []
     return []
